@@ -1,0 +1,242 @@
+"""Benchmark of the butterfly-interaction particle filter on one MI355X.
+
+Workload (default): the 8-D linear-Gaussian model (A = 0.9 I + 0.05 O, Q = I,
+H = I, R = 0.5 I), N = 2^20 particles, radix 64 (stages 64, 64, 64, 4),
+multinomial resampling, FP32 states and log-weights, FP64 log-normaliser;
+synthetic observations simulated from the model (seed 2). One "step" is one
+filter time step over all N particles: log-weight -> group resample ->
+gather -> propagate (+ estimate partials and the final reduction).
+
+Printed (one JSON line): particle-steps/s of the butterfly path with the
+observations already in device memory, the global-resampling bootstrap
+filter (r = N) on the same input and its speedup, p50/p99 step latency,
+the roofline of the step kernel (algorithmic bytes / measured time against
+the 8 TB/s HBM peak), and the FP64 oracle timed on the host as a baseline.
+
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--radix 64]
+       python bench.py --mode profile   (kernel-only run for rocprofv3)
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "pf_step_tile_lg8_n2p20_r64.json")
+KERNEL_SOURCES = ["paper_1812_01502_amd/csrc/pf_kernels.h", "paper_1812_01502_amd/csrc/pf_device.h"]
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(d: int, state_bytes: int, path: str) -> int:
+    """Bytes one particle-step must move. Butterfly (fused): read and write
+    x (d components) and the FP32 log-weight once. Global bootstrap filter:
+    the cheaper of re-reading x (4 d s) or storing a CDF and ancestor
+    (2 d s + 16); log-weights are all zero after a global resample."""
+    if path == "butterfly":
+        return 2 * (d * state_bytes + 4)
+    return min(4 * d * state_bytes, 2 * d * state_bytes + 16)
+
+
+def timed_run(flt, yd, steps, d):
+    import torch
+    torch.cuda.synchronize()
+    start = torch.cuda.Event(enable_timing=True)
+    stop = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    start.record()
+    flt.run(yd.data_ptr(), steps, d)
+    stop.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return wall, start.elapsed_time(stop) / 1e3
+
+
+def per_step_latency(flt, yd, steps, d):
+    import numpy as np
+    import torch
+    evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+           for _ in range(steps)]
+    torch.cuda.synchronize()
+    for j in range(steps):
+        evs[j][0].record()
+        flt.run(yd[j].data_ptr(), 1, d)
+        evs[j][1].record()
+    torch.cuda.synchronize()
+    us = np.array([a.elapsed_time(b) * 1e3 for a, b in evs])
+    return float(np.percentile(us, 50)), float(np.percentile(us, 99)), float(us.mean())
+
+
+def cpu_baseline(model, N, radix, ys, budget_s=12.0):
+    """The FP64 oracle as it stands, single-threaded, on the same workload:
+    as many time steps of N particles as fit in about budget_s seconds."""
+    from threadpoolctl import threadpool_limits
+    from oracle import ButterflyOracle
+    with threadpool_limits(limits=1):
+        orc = ButterflyOracle(model, N, radix, seed=202)
+        st = orc.init()
+        t0 = time.perf_counter()
+        n = 0
+        while n < len(ys):
+            st, _ = orc.step(st, ys[n], keep=False)
+            n += 1
+            if time.perf_counter() - t0 > budget_s:
+                break
+        el = time.perf_counter() - t0
+    return dict(value=N * n / el, unit="particle-steps/s", cores=1, kind="oracle",
+                sample=f"{n} time steps of N = {N} particles, radix {radix} "
+                       f"(stage cycle {orc.plan}), FP64 NumPy, 1 thread, {el:.1f} s")
+
+
+def load_traffic(path, n_launch_bytes):
+    """HBM traffic per launch from the committed rocprofv3 counter summary,
+    if it was taken on the current kernel sources; else None."""
+    try:
+        with open(path) as f:
+            prof = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if prof.get("kernel_source_hash") != kernel_source_hash():
+        return None
+    return prof.get("hbm_bytes_per_launch")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=500)
+    ap.add_argument("--warmup", type=int, default=20)
+    ap.add_argument("--radix", type=int, default=64)
+    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--extra-radices", default="2,4,32")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py runs on one GPU only: this build has no multi-GPU path "
+              "(--gpus must be 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1812_01502_amd as P
+    import workloads as W
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    P.load_library()
+    cfg = W.config("c2")
+    model, N, d = cfg["model"], args.n, cfg["model"].d
+    K, Wm = args.steps, args.warmup
+    _, ys = W.simulate(model, Wm + K, seed=cfg["seed_obs"])
+    yd = torch.tensor(ys, dtype=torch.float32, device="cuda").contiguous()
+    stream = torch.cuda.current_stream()
+
+    def make(radix):
+        return P.Filter(model, N, radix, seed=cfg["seed_pf"], history=4,
+                        stream=stream.cuda_stream)
+
+    if args.mode == "profile":
+        # step kernels only (for rocprofv3), then a plain copy of known size
+        flt = make(args.radix)
+        flt.run(yd.data_ptr(), Wm + K, d)
+        flt.sync()
+        flt.close()
+        src = torch.empty(1 << 27, dtype=torch.float32, device="cuda")   # 512 MiB
+        src.fill_(1.0)
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"profile_run": True, "copy_bytes": src.numel() * 4}))
+        return
+
+    # -- butterfly, headline radix ------------------------------------------
+    flt = make(args.radix)
+    plan = flt.info()["stages"]
+    flt.run(yd.data_ptr(), Wm, d)                     # warm-up steps
+    wall, ev_s = timed_run(flt, yd[Wm:], K, d)
+    value = N * K / wall
+    ms_step = wall / K * 1e3
+    p50, p99, mean_us = per_step_latency(flt, yd, min(K, Wm + K), d)
+    est = flt.estimate()
+    flt.close()
+    B = algorithmic_bytes(d, 4, "butterfly")
+    launch_bytes = B * N
+    avg_launch_s = ev_s / K                            # one step kernel per step
+    achieved = launch_bytes / avg_launch_s / 1e9
+    traffic = load_traffic(PROFILE_SUMMARY, launch_bytes)
+
+    # -- global bootstrap filter (r = N) ---------------------------------------
+    g = make(N)
+    g.run(yd.data_ptr(), Wm, d)
+    gwall, gev = timed_run(g, yd[Wm:], K, d)
+    gvalue = N * K / gwall
+    gp50, gp99, _ = per_step_latency(g, yd, min(K, Wm + K), d)
+    g.close()
+    Bg = algorithmic_bytes(d, 4, "global")
+
+    # -- other radices --------------------------------------------------------
+    per_radix = {}
+    for r in [int(v) for v in args.extra_radices.split(",") if v]:
+        f2 = make(r)
+        f2.run(yd.data_ptr(), Wm, d)
+        w2, e2 = timed_run(f2, yd[Wm:], K, d)
+        per_radix[str(r)] = dict(particle_steps_per_s=N * K / w2, ms_per_step=w2 / K * 1e3,
+                                 hbm_frac=B * N / (e2 / K) / 1e9 / HBM_PEAK_GBS,
+                                 stages=f2.info()["stages"])
+        f2.close()
+    per_radix[str(args.radix)] = dict(particle_steps_per_s=value, ms_per_step=ms_step,
+                                      hbm_frac=achieved / HBM_PEAK_GBS, stages=plan)
+
+    out = {
+        "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
+        "value": value,
+        "unit": "particle-steps/s",
+        "n_gpus": 1,
+        "steps": K,
+        "warmup": Wm,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"lg8 N=2^{N.bit_length() - 1} radix {args.radix}",
+                   "n_particles": N, "state_dim": d, "radix": args.radix, "stages": plan,
+                   "resampler": "multinomial", "steps_per_run": K, "observations": "device"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS,
+                     "traffic": traffic,
+                     "kernel": "pf_step_tile (fused butterfly step)",
+                     "bytes_per_particle_step": B, "bytes_per_launch": launch_bytes,
+                     "avg_launch_us": avg_launch_s * 1e6},
+        "latency_us": {"p50": p50, "p99": p99, "mean": mean_us},
+        "global_bpf": {"particle_steps_per_s": gvalue, "ms_per_step": gwall / K * 1e3,
+                       "speedup_butterfly_over_global": value / gvalue,
+                       "bytes_per_particle_step": Bg,
+                       "hbm_frac_algorithmic": Bg * N / (gev / K) / 1e9 / HBM_PEAK_GBS,
+                       "latency_us": {"p50": gp50, "p99": gp99}},
+        "per_radix": per_radix,
+        "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
+    }
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(model, N, args.radix, ys)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

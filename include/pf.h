@@ -1,0 +1,205 @@
+/*
+ * pf.h - C-ABI of the butterfly-interaction bootstrap particle filter on
+ * MI355X (gfx950).
+ *
+ * Method: Heine, Whiteley, Cemgil, "Parallelising Particle Filters with
+ * Butterfly Interactions" (arXiv 1812.01502).
+ *
+ *  - The filter is Algorithm 1 (particle filter) of Section 1.1 for the hidden
+ *    Markov model of eq. HMM: X_0 ~ pi_0, X_n | X_{n-1} ~ f(X_{n-1}, .),
+ *    Y_n | X_n ~ g(X_n, .). The observations are fixed inputs (Section 1.3).
+ *  - The particle count is N = mM with the interaction pattern A_1..A_S of
+ *    eq. A matrices (Section 1.2, Assumption A1). Here the pattern is given
+ *    as a radix r: the particle index is written in mixed radix (digits of
+ *    radix r from the least significant end, the top digit taking what is
+ *    left) and stage k lets the particles that differ only in digit k
+ *    interact (Lemma 1 for r = 2; Remark 1 allows any such family).
+ *  - One time step t runs one stage, k = t mod S (the stage-wise scheme of
+ *    Section 1.2 with the rotation proposed in Section 6.4): log-weight with
+ *    y_t, resample inside each group with probability proportional to the
+ *    weights (Algorithm 3), carry the group-mean weight (eq. V_defn_proofs),
+ *    gather the ancestors, propagate with f.
+ *  - r >= N is the plain bootstrap filter with global multinomial resampling
+ *    (Algorithms 1 and 2).
+ *
+ * Conventions
+ *  - Every function returns a pf_status (0 = PF_OK, < 0 = error) and never
+ *    aborts or throws. After a device error a handle is poisoned: later
+ *    calls return PF_E_STATE until pf_destroy.
+ *  - All pointers marked "host" are ordinary host memory, read or written
+ *    before the call returns. Pointers marked "device" are HIP device
+ *    memory on the handle's device.
+ *  - A handle owns all its device buffers. Model arrays are copied at
+ *    create time; the caller keeps ownership of what it passes.
+ *  - Work is enqueued on the HIP stream given at create time (NULL = the
+ *    default stream). Calls that return data to the host synchronise that
+ *    stream. A handle is not thread-safe; distinct handles are independent.
+ *  - Random numbers: Philox4x32-10 (Salmon et al., SC'11) keyed by
+ *    `seed`, counter (particle pair, step, block, stream_id). Results depend
+ *    only on (model, N, radix, resampler, dtype, seed, stream_id, y), not on
+ *    launch shapes.
+ */
+#ifndef PF_H
+#define PF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define PF_MAX_DIM 16
+
+typedef enum {
+  PF_OK = 0,
+  PF_E_INVALID = -1,     /* bad argument (size, pointer, radix, dimension) */
+  PF_E_UNSUPPORTED = -2, /* valid but not supported by this build */
+  PF_E_OOM = -3,         /* device allocation failed */
+  PF_E_HIP = -4,         /* a HIP runtime call failed */
+  PF_E_NUMERIC = -5,     /* non-finite observation or weights */
+  PF_E_STATE = -6        /* handle poisoned by an earlier error */
+} pf_status;
+
+typedef enum { PF_MODEL_LG = 0, PF_MODEL_SV = 1 } pf_model_kind;
+typedef enum { PF_RESAMPLE_MULTINOMIAL = 0, PF_RESAMPLE_SYSTEMATIC = 1 } pf_resampler;
+/* Storage type of the particle states. F32 and BF16 compute in FP32 with
+ * FP32 log-weights; F64 computes and stores in FP64. The running
+ * log-normaliser is always FP64. */
+typedef enum { PF_DTYPE_F32 = 0, PF_DTYPE_BF16 = 1, PF_DTYPE_F64 = 2 } pf_dtype;
+
+/* Model (host memory, copied at create). Section 1.1, eq. HMM.
+ * LG  (kind = PF_MODEL_LG), all matrices row-major d x d, vectors length d:
+ *       x_0 = m0 + P0_chol z,  x_n = A x_{n-1} + Q_chol z,
+ *       y_n = H x_n + R_chol e,  z, e ~ N(0, I_d);
+ *     Q_chol, R_chol, P0_chol lower-triangular with positive diagonal.
+ *     g(x, y) is the N(H x, R) density, normalising constant included.
+ * SV  (kind = PF_MODEL_SV, d = 1):
+ *       x_0 ~ N(0, sigma^2 / (1 - phi^2)),  x_n = phi x_{n-1} + sigma z,
+ *       y_n = beta exp(x_n / 2) e.                                        */
+typedef struct {
+  int32_t kind;
+  int32_t d;                /* 1 <= d <= PF_MAX_DIM (SV: 1) */
+  const double* A;
+  const double* Q_chol;
+  const double* H;
+  const double* R_chol;
+  const double* m0;
+  const double* P0_chol;
+  double phi, sigma, beta;  /* SV only; |phi| < 1, sigma > 0, beta > 0 */
+} pf_model;
+
+typedef struct {
+  uint64_t n_particles;  /* N: power of two, 2 <= N <= 2^30 */
+  uint64_t radix;        /* r: power of two >= 2; r >= N selects the global path */
+  int32_t resampler;     /* pf_resampler */
+  int32_t state_dtype;   /* pf_dtype */
+  uint64_t seed;         /* Philox key */
+  uint32_t stream_id;    /* Philox counter word 3 (identity of the filter) */
+  uint32_t history;      /* per-step estimate records kept on device (0 -> 1) */
+  uint32_t keep_ancestors; /* nonzero: record each step's ancestor indices */
+  uint32_t reserved;
+} pf_config;
+
+/* Estimate of one completed step t (R9 of the design: the weighted cloud
+ * before resampling, i.e. the filtering law of x_t given y_0..y_t). */
+typedef struct {
+  uint32_t t;              /* step index the record belongs to */
+  uint32_t stage;          /* butterfly stage k = t mod S used by the step */
+  uint32_t radix;          /* radix r_k of that stage */
+  uint32_t valid;          /* 1 if the step has run */
+  double log_normaliser;   /* running log p-hat(y_0..y_t), FP64 */
+  double ess;              /* (sum w)^2 / (N sum w^2), in [1/N, 1] */
+  double max_log_weight;   /* max_i l_i of the step */
+  double next_offset;      /* max of the new log-weights (subtracted next step) */
+  double mean[PF_MAX_DIM]; /* weighted mean of x_t */
+  double var[PF_MAX_DIM];  /* weighted variance of x_t */
+} pf_estimate_t;
+
+typedef struct {
+  uint64_t n_particles;
+  uint32_t d;
+  uint32_t n_stages;        /* S */
+  uint32_t radices[32];     /* r_0..r_{S-1} */
+  uint32_t global_path;     /* 1 if r >= N */
+  uint32_t state_dtype;
+  uint64_t device_bytes;    /* device memory held by the handle */
+  uint32_t t;               /* completed steps */
+  uint32_t tile_elems[32];  /* particles per workgroup tile, per stage */
+} pf_info_t;
+
+typedef struct pf_handle pf_handle;
+
+/* Create a filter and run the initialisation of Algorithm 1 (x_0 ~ pi_0,
+ * unit weights) on `hip_stream` (a hipStream_t, or NULL). On success *out
+ * owns the handle. Errors: PF_E_INVALID (N not a power of two, radix < 2
+ * or not a power of two, d out of range, NULL pointers, non-finite or
+ * non-positive-definite parameters), PF_E_UNSUPPORTED (a stage radix the
+ * device kernels cannot tile), PF_E_OOM, PF_E_HIP. */
+pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_stream,
+                    pf_handle** out);
+
+/* Release every device buffer of the handle. NULL is accepted. */
+pf_status pf_destroy(pf_handle* h);
+
+/* Re-run the initialisation (t = 0, log-normaliser 0) with the same seed. */
+pf_status pf_reset(pf_handle* h);
+
+/* One time step (Algorithm 1 loop body with one butterfly stage) using the
+ * observation `y_host` (host, d doubles). Asynchronous. Errors:
+ * PF_E_NUMERIC for a non-finite observation, PF_E_STATE if poisoned. */
+pf_status pf_step(pf_handle* h, const double* y_host);
+
+/* `n_steps` consecutive time steps reading observation j from
+ * `y_dev + j * y_stride` (device; elements of the compute type: float for
+ * F32/BF16 states, double for F64; y_stride >= d). With use_graph != 0 the
+ * launches are captured in a HIP graph and replayed once. Asynchronous.
+ * Non-finite device observations are not checked. */
+pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_stride,
+                 int32_t use_graph);
+
+/* Estimate of the last completed step (synchronises the stream). `out`
+ * host, caller-owned. PF_E_STATE if no step has run. */
+pf_status pf_estimate(pf_handle* h, pf_estimate_t* out);
+
+/* The last min(n_max, history, steps run) records, oldest first (host
+ * output; synchronises). *n_out receives the count. */
+pf_status pf_history(pf_handle* h, pf_estimate_t* out, uint32_t n_max, uint32_t* n_out);
+
+/* Current particle cloud (synchronises): x_host receives d planes of N
+ * values in the storage type (plane j = component j of every particle),
+ * logw_host receives N log-weights normalised so that their max is 0
+ * (float, or double for F64 states); either may be NULL. *t_out (may be
+ * NULL) receives the number of completed steps and *log_norm (may be NULL)
+ * the running log-normaliser. */
+pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_out,
+                       double* log_norm);
+
+/* Overwrite the particle cloud (host input, same layouts as pf_get_state)
+ * and set the step counter and log-normaliser. Used to start a step from a
+ * given cloud. logw_host may be NULL (all zero). */
+pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, uint32_t t,
+                       double log_norm);
+
+/* Ancestor index a(i) (into the previous cloud) of every particle of the
+ * last step (host output, N uint32; synchronises). Requires
+ * cfg.keep_ancestors, else PF_E_STATE. */
+pf_status pf_get_ancestors(pf_handle* h, uint32_t* anc_host);
+
+/* Sizes and plan of the handle (host output). */
+pf_status pf_info(pf_handle* h, pf_info_t* out);
+
+/* Wait for all work of the handle (hipStreamSynchronize). */
+pf_status pf_sync(pf_handle* h);
+
+/* Static description of a status code. */
+const char* pf_status_string(pf_status s);
+
+/* Last error message of the handle (never NULL; "" if none). With h == NULL
+ * the message of the last failed pf_create of this thread. */
+const char* pf_last_error(const pf_handle* h);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PF_H */

@@ -1,0 +1,195 @@
+"""Butterfly-interaction bootstrap particle filter on MI355X (gfx950).
+
+Python binding over the C-ABI of ``include/pf.h`` (``libpf.so``, hand-written
+HIP kernels). This module only marshals arguments: model parameters are
+copied into the library, observations go by value (``step``) or as a device
+array (``run``), and results come back as NumPy arrays.
+
+Method: Heine, Whiteley, Cemgil, "Parallelising Particle Filters with
+Butterfly Interactions" (arXiv 1812.01502): Algorithm 1 with one stage of
+augmented resampling (Algorithm 3, eq. ``A matrices`` generalised to radix
+r) per time step, the stage rotating with the step.
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _lib as L
+
+__all__ = ["Filter", "PfError", "load_library", "DTYPES", "RESAMPLERS"]
+
+DTYPES = {"f32": L.PF_DTYPE_F32, "bf16": L.PF_DTYPE_BF16, "f64": L.PF_DTYPE_F64}
+RESAMPLERS = {"multinomial": L.PF_RESAMPLE_MULTINOMIAL, "systematic": L.PF_RESAMPLE_SYSTEMATIC}
+
+
+class PfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
+        self.status = status
+
+
+def load_library():
+    return L.load()
+
+
+def _dptr(a):
+    return a.ctypes.data_as(L.DPTR)
+
+
+class Filter:
+    """One particle filter on the GPU.
+
+    ``model`` needs the attributes ``kind`` ("lg" or "sv"), ``d`` and, for LG,
+    ``A, Q_chol, H, R_chol, m0, P0_chol`` (FP64 arrays); for SV ``phi, sigma,
+    beta``. ``radix >= n`` selects the global bootstrap filter.
+    """
+
+    def __init__(self, model, n: int, radix: int, resampler: str = "multinomial",
+                 dtype: str = "f32", seed: int = 0, stream_id: int = 0, history: int = 1,
+                 keep_ancestors: bool = False, stream: int | None = None):
+        self._lib = L.load()
+        self.d = int(model.d)
+        self.n = int(n)
+        self.dtype = dtype
+        self._keep = []
+        m = L.PfModel()
+        m.d = self.d
+        if model.kind == "lg":
+            m.kind = L.PF_MODEL_LG
+            for nm in ("A", "Q_chol", "H", "R_chol", "P0_chol"):
+                arr = np.ascontiguousarray(np.asarray(getattr(model, nm), dtype=np.float64))
+                self._keep.append(arr)
+                setattr(m, nm, _dptr(arr))
+            m0 = np.ascontiguousarray(np.asarray(model.m0, dtype=np.float64))
+            self._keep.append(m0)
+            m.m0 = _dptr(m0)
+        elif model.kind == "sv":
+            m.kind = L.PF_MODEL_SV
+            m.phi, m.sigma, m.beta = float(model.phi), float(model.sigma), float(model.beta)
+        else:
+            raise ValueError(f"unknown model kind {model.kind!r}")
+        c = L.PfConfig()
+        c.n_particles = self.n
+        c.radix = int(radix)
+        c.resampler = RESAMPLERS[resampler]
+        c.state_dtype = DTYPES[dtype]
+        c.seed = int(seed)
+        c.stream_id = int(stream_id)
+        c.history = int(history)
+        c.keep_ancestors = 1 if keep_ancestors else 0
+        h = ctypes.c_void_p()
+        st = self._lib.pf_create(ctypes.byref(m), ctypes.byref(c),
+                                 ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))
+        if st != L.PF_OK:
+            raise PfError(st, self._lib.pf_last_error(None).decode())
+        self._h = h
+        self._x_dtype = {"f32": np.float32, "bf16": np.uint16, "f64": np.float64}[dtype]
+        self._w_dtype = np.float64 if dtype == "f64" else np.float32
+
+    # -- plumbing ----------------------------------------------------------
+    def _check(self, st):
+        if st != L.PF_OK:
+            raise PfError(st, self._lib.pf_last_error(self._h).decode())
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -- the filter --------------------------------------------------------
+    def step(self, y):
+        y = np.ascontiguousarray(np.asarray(y, dtype=np.float64).reshape(self.d))
+        self._check(self._lib.pf_step(self._h, _dptr(y)))
+
+    def run(self, y_dev_ptr: int, n_steps: int, stride: int | None = None, use_graph: bool = False):
+        """``n_steps`` steps reading observations from a device array (pointer
+        ``y_dev_ptr``, compute dtype, ``stride`` elements per step)."""
+        self._check(self._lib.pf_run(self._h, ctypes.c_void_p(int(y_dev_ptr)), int(n_steps),
+                                     int(stride if stride is not None else self.d),
+                                     1 if use_graph else 0))
+
+    def sync(self):
+        self._check(self._lib.pf_sync(self._h))
+
+    def reset(self):
+        self._check(self._lib.pf_reset(self._h))
+
+    @staticmethod
+    def _rec(e: L.PfEstimate, d: int) -> dict:
+        return dict(t=e.t, stage=e.stage, radix=e.radix, valid=e.valid,
+                    log_norm=e.log_normaliser, ess=e.ess, max_ell=e.max_log_weight,
+                    offset=e.next_offset, mean=np.array(e.mean[:d]), var=np.array(e.var[:d]))
+
+    def estimate(self) -> dict:
+        e = L.PfEstimate()
+        self._check(self._lib.pf_estimate(self._h, ctypes.byref(e)))
+        return self._rec(e, self.d)
+
+    def history(self, n_max: int) -> list:
+        buf = (L.PfEstimate * n_max)()
+        n = ctypes.c_uint32()
+        self._check(self._lib.pf_history(self._h, buf, n_max, ctypes.byref(n)))
+        return [self._rec(buf[i], self.d) for i in range(n.value)]
+
+    def get_state(self):
+        """``(x (d, N) in the storage dtype, logW (N,), t, log_norm)``."""
+        x = np.empty((self.d, self.n), dtype=self._x_dtype)
+        w = np.empty(self.n, dtype=self._w_dtype)
+        t = ctypes.c_uint32()
+        ln = ctypes.c_double()
+        self._check(self._lib.pf_get_state(self._h, x.ctypes.data_as(ctypes.c_void_p),
+                                           w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t),
+                                           ctypes.byref(ln)))
+        return x, w, t.value, ln.value
+
+    def set_state(self, x, logw=None, t: int = 0, log_norm: float = 0.0):
+        x = np.ascontiguousarray(np.asarray(x, dtype=self._x_dtype).reshape(self.d, self.n))
+        wp = None
+        if logw is not None:
+            w = np.ascontiguousarray(np.asarray(logw, dtype=self._w_dtype).reshape(self.n))
+            wp = w.ctypes.data_as(ctypes.c_void_p)
+        self._check(self._lib.pf_set_state(self._h, x.ctypes.data_as(ctypes.c_void_p), wp,
+                                           int(t), float(log_norm)))
+
+    def ancestors(self) -> np.ndarray:
+        a = np.empty(self.n, dtype=np.uint32)
+        self._check(self._lib.pf_get_ancestors(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))
+        return a
+
+    def info(self) -> dict:
+        i = L.PfInfo()
+        self._check(self._lib.pf_info(self._h, ctypes.byref(i)))
+        S = i.n_stages
+        return dict(n=i.n_particles, d=i.d, stages=list(i.radices[:S]),
+                    tile_elems=list(i.tile_elems[:S]), global_path=bool(i.global_path),
+                    device_bytes=i.device_bytes, t=i.t)
+
+
+def bf16_to_f32(u16: np.ndarray) -> np.ndarray:
+    """BF16 bit patterns (uint16) to FP32."""
+    return (np.asarray(u16, dtype=np.uint32) << 16).view(np.float32)
+
+
+def f32_to_bf16(x: np.ndarray) -> np.ndarray:
+    """FP32 to BF16 bit patterns, round to nearest even (finite inputs)."""
+    u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    u = u + 0x7FFF + ((u >> 16) & 1)
+    return (u >> 16).astype(np.uint16)

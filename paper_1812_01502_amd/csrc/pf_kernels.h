@@ -1,0 +1,808 @@
+// pf_kernels.h - HIP kernels of one particle-filter time step on gfx950.
+//
+// Butterfly path (radix r < N), one fused kernel per step:
+//   phase A  coalesced load of a tile of r x C particles (C contiguous
+//            columns per group row, rows at the stage stride R), log-weight
+//            l = logW - offset + log g(x, y_t), Philox randoms, per-tile
+//            estimate partials; states and scalars staged in LDS
+//   phase B  per group (a column of the tile): max, exp, inclusive scan,
+//            carried weight m_G + ln c_{r-1} - ln r, inverse-CDF draw.
+//            r <= 64: one wave segment per group (cross-lane shuffles);
+//            r > 64: 64-member chunks with LDS chunk prefixes.
+//   phase C  gather of the ancestor from LDS, propagation with the
+//            step's normals, coalesced store of x and the new log-weight
+//   tail     the last tile to finish reduces all tile partials in FP64 in a
+//            fixed order (estimate record, log-normaliser, next offset).
+// Global path (r >= N): weight + tile scan, grid prefix (+ finalize),
+// draw + gather + propagate.
+#pragma once
+
+#include "pf_device.h"
+
+namespace pfk {
+
+template <typename T, typename S> struct StepArgs {
+  const S* x_in;
+  S* x_out;
+  const T* lw_in;
+  T* lw_out;
+  uint32_t* anc;            // nullable: global ancestor index per particle
+  const T* y_dev;           // nullable: observation (d values) in device memory
+  T y_val[kMaxDim];         // observation passed by value when y_dev == nullptr
+  const ModelParams<T>* mp;
+  T* partials;
+  Ctl* ctl;
+  pf_estimate_t* hist;
+  uint32_t hist_cap;
+  uint32_t d;
+  uint64_t N;
+  uint32_t log2r, log2R, log2C, pad;  // stage radix, stride, tile columns, LDS row pad
+  uint32_t t, k;
+  uint32_t ntiles;
+  uint32_t radix;            // r_k (N on the global path)
+  uint32_t k0, k1, sid;
+  int32_t systematic;
+  int32_t lw_nonzero;        // global path: read logW (else all log-weights are 0)
+  T lnr;                     // ln r
+  // global path scratch
+  T* gcdf;                   // within-tile inclusive CDF (N)
+  T* gcoarse;                // every 64th CDF value (N / 64)
+  double* gpre;              // tile prefix, ntiles + 1 entries
+  double* gscale;            // e^{m_b - M}, ntiles entries
+};
+
+// ---------------------------------------------------------------------------
+// Initialisation (Algorithm 1): x_0 = prior(z(tau = 0)), logW = 0, control
+// block reset.
+// ---------------------------------------------------------------------------
+template <int D, int MK, typename T, typename S>
+__global__ void __launch_bounds__(256) pf_init_kernel(StepArgs<T, S> a) {
+  const uint64_t npair = a.N >> 1;
+  const int d = (int)a.d;
+  for (uint64_t p = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; p < npair;
+       p += (uint64_t)gridDim.x * blockDim.x) {
+    T z0[D], z1[D], x0[D], x1[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) z0[j] = z1[j] = 0;
+    pair_normals<D, T>((uint32_t)p, 0u, a.sid, a.k0, a.k1, d, z0, z1);
+    Model<D, MK, T>::prior(a.mp, z0, x0);
+    Model<D, MK, T>::prior(a.mp, z1, x1);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * a.N + 2 * p, x0[j], x1[j]);
+    a.lw_out[2 * p] = 0;
+    a.lw_out[2 * p + 1] = 0;
+  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    a.ctl->log_norm = 0.0;
+    a.ctl->offset = 0.0;
+    for (int j = 0; j < kMaxDim; ++j) a.ctl->shift[j] = 0.0;
+    a.ctl->counter = 0u;
+    a.ctl->t = 0u;
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block-wide helpers.
+// ---------------------------------------------------------------------------
+template <typename T, int NT>
+__device__ __forceinline__ T block_max(T v, T* red /* NT/64 */) {
+  v = wave_max(v);
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) red[wv] = v;
+  __syncthreads();
+  T m = red[0];
+#pragma unroll
+  for (int i = 1; i < NT / 64; ++i) m = fmaxT(m, red[i]);
+  __syncthreads();
+  return m;
+}
+
+// Arguments of the final reduction.
+struct FinArgs {
+  Ctl* ctl;
+  pf_estimate_t* hist;
+  uint32_t hist_cap, t, k, radix, d;
+  uint64_t N;
+};
+
+template <typename T> __device__ __forceinline__ double ld_partial(const T* p, bool coherent) {
+  return coherent ? (double)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
+                  : (double)*p;
+}
+
+__device__ __forceinline__ double wave_sum_d(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
+  return v;
+}
+__device__ __forceinline__ double wave_max_d(double v) {
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
+  return v;
+}
+
+// Final FP64 reduction of the tile partials by one block, in a fixed order
+// (thread i takes tiles i, i + NT, ...; waves reduce by a fixed butterfly;
+// wave results are added in wave order). Writes the estimate record of step
+// t and advances the control block. `red` needs (NT/64) * (5 + 2D) doubles.
+template <int D, typename T, int NT>
+__device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, uint32_t ntiles,
+                                  double* red, bool coherent, bool reset_counter) {
+  constexpr int PS = partial_stride(D);
+  constexpr int NW = NT / 64;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  double m = -INFINITY, lwmax = -INFINITY;
+  for (uint32_t b = tid; b < ntiles; b += NT) {
+    m = fmax(m, ld_partial(part + (size_t)b * PS, coherent));
+    lwmax = fmax(lwmax, ld_partial(part + (size_t)b * PS + 4, coherent));
+  }
+  m = wave_max_d(m);
+  lwmax = wave_max_d(lwmax);
+  if (lane == 0) {
+    red[wv * 2] = m;
+    red[wv * 2 + 1] = lwmax;
+  }
+  __syncthreads();
+  double M = red[0], LWM = red[1];
+  for (int w = 1; w < NW; ++w) {
+    M = fmax(M, red[w * 2]);
+    LWM = fmax(LWM, red[w * 2 + 1]);
+  }
+  __syncthreads();
+  double acc[PS];
+#pragma unroll
+  for (int v = 0; v < PS; ++v) acc[v] = 0.0;
+  for (uint32_t b = tid; b < ntiles; b += NT) {
+    const T* pr = part + (size_t)b * PS;
+    const double e = exp(ld_partial(pr, coherent) - M);
+    acc[1] += e * ld_partial(pr + 1, coherent);
+    acc[2] += e * e * ld_partial(pr + 2, coherent);
+    acc[3] += ld_partial(pr + 3, coherent);
+#pragma unroll
+    for (int v = 5; v < PS; ++v) acc[v] += e * ld_partial(pr + v, coherent);
+  }
+#pragma unroll
+  for (int v = 1; v < PS; ++v) {
+    if (v == 4) continue;
+    if (v >= 5 + (int)f.d && v < 5 + D) continue;
+    if (v >= 5 + D + (int)f.d) continue;
+    acc[v] = wave_sum_d(acc[v]);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int v = 0; v < PS; ++v) red[wv * PS + v] = acc[v];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot[PS];
+#pragma unroll
+    for (int v = 0; v < PS; ++v) {
+      tot[v] = red[v];
+      for (int w = 1; w < NW; ++w) tot[v] += red[w * PS + v];
+    }
+    const double S = tot[1], sw2 = tot[2], swin = tot[3];
+    pf_estimate_t* rec = f.hist + (f.t % f.hist_cap);
+    const double dlog = (M + log(S)) - log(swin);
+    const double ln = f.ctl->log_norm + dlog;
+    rec->t = f.t;
+    rec->stage = f.k;
+    rec->radix = f.radix;
+    rec->valid = 1u;
+    rec->log_normaliser = ln;
+    rec->ess = S * S / ((double)f.N * sw2);
+    rec->max_log_weight = M;
+    rec->next_offset = LWM;
+#pragma unroll
+    for (int j = 0; j < kMaxDim; ++j) {
+      double mean = 0.0, var = 0.0;
+      if (j < D && j < (int)f.d) {
+        const double m1 = tot[5 + (j < D ? j : 0)] / S;
+        const double m2 = tot[5 + D + (j < D ? j : 0)] / S;
+        mean = f.ctl->shift[j] + m1;
+        var = fmax(m2 - m1 * m1, 0.0);
+        f.ctl->shift[j] = mean;
+      }
+      rec->mean[j] = mean;
+      rec->var[j] = var;
+    }
+    f.ctl->log_norm = ln;
+    f.ctl->offset = LWM;
+    f.ctl->t = f.t + 1;
+    if (reset_counter)
+      __hip_atomic_store(&f.ctl->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+template <typename T, typename S> __device__ __forceinline__ FinArgs fin_args(const StepArgs<T, S>& a) {
+  FinArgs f;
+  f.ctl = a.ctl;
+  f.hist = a.hist;
+  f.hist_cap = a.hist_cap;
+  f.t = a.t;
+  f.k = a.k;
+  f.radix = a.radix;
+  f.d = a.d;
+  f.N = a.N;
+  return f;
+}
+
+// Partial sums of one tile from per-thread register values. Every thread
+// holds nloc (l, x, logW) triples; returns after thread PS-1 of the block
+// has written the record. `red` needs (NT/64) * (5 + 2D) values of T.
+template <int D, typename T, int NT, int NLOC>
+__device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[NLOC][D],
+                                              const T (&lwn)[NLOC], const T (&shift)[D], int d,
+                                              T mtile, T* red, T* out /* PS values */) {
+  constexpr int PS = partial_stride(D);
+  T s = 0, sw2 = 0, swin = 0, a1[D], a2[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) a1[j] = a2[j] = 0;
+#pragma unroll
+  for (int e = 0; e < NLOC; ++e) {
+    const T w = fexp(l[e] - mtile);
+    s += w;
+    sw2 += w * w;
+    swin += fexp(lwn[e]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      const T dx = x[e][j] - shift[j];
+      const T wd = w * dx;
+      a1[j] += wd;
+      a2[j] += wd * dx;
+    }
+  }
+  s = wave_sum(s);
+  sw2 = wave_sum(sw2);
+  swin = wave_sum(swin);
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    if (j < d) {
+      a1[j] = wave_sum(a1[j]);
+      a2[j] = wave_sum(a2[j]);
+    }
+  }
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  if (lane == 0) {
+    T* rw = red + wv * PS;
+    rw[1] = s;
+    rw[2] = sw2;
+    rw[3] = swin;
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      rw[5 + j] = a1[j];
+      rw[5 + D + j] = a2[j];
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x < PS) {
+    const int v = threadIdx.x;
+    T acc = 0;
+    if (v == 0) acc = mtile;
+    else if (v != 4) {
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) acc += red[w * PS + v];
+    }
+    // device-coherent store: read by whichever tile finishes last
+    if (v != 4) __hip_atomic_store(&out[v], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Tile coordinates. A tile holds E = r C particles: column c of row q.
+// wide (R >= C): rows are C contiguous particles at stride R.
+// narrow (R < C): the tile is one contiguous run of E particles.
+// ---------------------------------------------------------------------------
+struct TileGeo {
+  uint32_t log2r, log2R, log2C;
+  bool wide;
+  uint64_t base;
+};
+
+__device__ __forceinline__ TileGeo tile_geo(uint32_t tile, uint32_t log2r, uint32_t log2R,
+                                            uint32_t log2C) {
+  TileGeo g;
+  g.log2r = log2r;
+  g.log2R = log2R;
+  g.log2C = log2C;
+  g.wide = log2R >= log2C;
+  if (g.wide) {
+    const uint32_t sh = log2R - log2C;
+    const uint64_t hi = tile >> sh;
+    const uint64_t lo0 = (uint64_t)(tile & ((1u << sh) - 1u)) << log2C;
+    g.base = (hi << (log2r + log2R)) + lo0;
+  } else {
+    g.base = (uint64_t)tile << (log2r + log2C);
+  }
+  return g;
+}
+
+__device__ __forceinline__ void tile_coords(const TileGeo& g, uint32_t f, uint32_t& q, uint32_t& c,
+                                            uint64_t& gi) {
+  if (g.wide) {
+    q = f >> g.log2C;
+    c = f & ((1u << g.log2C) - 1u);
+    gi = g.base + ((uint64_t)q << g.log2R) + c;
+  } else {
+    const uint32_t sh = g.log2r + g.log2R;
+    const uint32_t hb = f >> sh;
+    const uint32_t rem = f & ((1u << sh) - 1u);
+    q = rem >> g.log2R;
+    c = (hb << g.log2R) | (rem & ((1u << g.log2R) - 1u));
+    gi = g.base + f;
+  }
+}
+
+// Block index -> tile: each of the 8 XCDs (blocks are dealt round-robin)
+// gets a contiguous range of tiles, so neighbouring column chunks share
+// the XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
+  if ((nb & 7u) != 0u) return b;
+  return (b & 7u) * (nb >> 3) + (b >> 3);
+}
+
+// Bump allocator over the dynamic LDS block: offsets are plain integers so
+// every carved pointer stays an LDS (address space 3) pointer.
+struct LdsCarve {
+  size_t off = 0;
+  __device__ __forceinline__ size_t take(size_t bytes) {
+    const size_t o = off;
+    off = (off + bytes + 15) & ~(size_t)15;
+    return o;
+  }
+};
+
+// LDS bytes of a tile kernel (must match the carve in pf_step_tile).
+__host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint32_t r, uint32_t C,
+                                                 uint32_t pad, int NT, bool blockpath) {
+  const size_t E = (size_t)r * C;
+  const size_t P = r + pad;
+  size_t b = 0;
+  auto add = [&](size_t n) { b = (b + n + 15) & ~(size_t)15; };
+  add((size_t)d * E * tsz);      // xs
+  add(C * P * tsz);              // l / cdf
+  add(C * P * tsz);              // uniforms
+  add(C * P * 4);                // ancestor positions
+  add(C * tsz);                  // carried weight per column
+  add((size_t)(NT / 64) * (5 + 2 * D) * tsz);  // reduction scratch
+  if (blockpath) {
+    add((E / 64) * tsz);  // chunk max
+    add((E / 64) * tsz);  // chunk sums
+    add(C * tsz);         // column max
+    add(C * tsz);         // column total
+  }
+  size_t fin = (size_t)(NT / 64) * (5 + 2 * D) * 8;  // finalize scratch (doubles), reuses the front
+  return b > fin ? b : fin;
+}
+
+// ---------------------------------------------------------------------------
+// Fused butterfly step (radix r < N). One block per tile of r x C particles.
+// ---------------------------------------------------------------------------
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
+__global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  constexpr int NLOC = 2 * PPT;
+  constexpr int PS = partial_stride(D);
+  const int d = (int)a.d;
+  const uint32_t log2r = a.log2r, log2C = a.log2C;
+  const uint32_t r = 1u << log2r, C = 1u << log2C;
+  const uint32_t E = r << log2C;
+  const uint32_t P = r + a.pad;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+
+  // LDS carve (tile_lds_bytes)
+  LdsCarve lc;
+  T* xs = reinterpret_cast<T*>(smem + lc.take((size_t)d * E * sizeof(T)));
+  T* scl = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
+  T* scu = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
+  int* sca = reinterpret_cast<int*>(smem + lc.take((size_t)C * P * sizeof(int)));
+  T* colw = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
+  T* red = reinterpret_cast<T*>(smem + lc.take((size_t)(NT / 64) * PS * sizeof(T)));
+  T* chm = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
+  T* chs = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
+  T* colm = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
+  T* coltot = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
+
+  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
+  const uint64_t N = a.N;
+  const T off = (T)a.ctl->offset;
+  T y[D], shift[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    y[j] = 0;
+    shift[j] = 0;
+    if (j < d) {
+      y[j] = a.y_dev ? a.y_dev[j] : a.y_val[j];
+      shift[j] = (T)a.ctl->shift[j];
+    }
+  }
+  const uint32_t tau = a.t + 1u;
+
+  // ---- phase A: load, log-weight, randoms ---------------------------------
+  T lr[NLOC], xr[NLOC][D], zr[NLOC][D], lwn[NLOC];
+  T tmax = -INFINITY;
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const uint32_t f0 = 2u * (tid + it * NT);
+    uint32_t q0, c0, q1, c1;
+    uint64_t g0, g1;
+    tile_coords(geo, f0, q0, c0, g0);
+    tile_coords(geo, f0 + 1, q1, c1, g1);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      xr[2 * it][j] = xr[2 * it + 1][j] = 0;
+      zr[2 * it][j] = zr[2 * it + 1][j] = 0;
+      if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + g0, xr[2 * it][j], xr[2 * it + 1][j]);
+    }
+    T w0, w1;
+    Pair<T, T>::load(a.lw_in + g0, w0, w1);
+    lwn[2 * it] = w0 - off;
+    lwn[2 * it + 1] = w1 - off;
+    lr[2 * it] = lwn[2 * it] + Model<D, MK, T>::log_g(a.mp, xr[2 * it], y);
+    lr[2 * it + 1] = lwn[2 * it + 1] + Model<D, MK, T>::log_g(a.mp, xr[2 * it + 1], y);
+    tmax = fmaxT(tmax, fmaxT(lr[2 * it], lr[2 * it + 1]));
+    T u0, u1;
+    pair_randoms<D, T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, d, u0, u1, zr[2 * it],
+                       zr[2 * it + 1]);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (j < d) {
+        xs[(size_t)j * E + (q0 << log2C) + c0] = xr[2 * it][j];
+        xs[(size_t)j * E + (q1 << log2C) + c1] = xr[2 * it + 1][j];
+      }
+    }
+    scl[c0 * P + q0] = lr[2 * it];
+    scl[c1 * P + q1] = lr[2 * it + 1];
+    scu[c0 * P + q0] = u0;
+    scu[c1 * P + q1] = u1;
+  }
+  // estimate partials relative to the tile max
+  const T mtile = block_max<T, NT>(tmax, red);
+  T* prt = a.partials + (size_t)tile * PS;
+  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, shift, d, mtile, red, prt);
+  __syncthreads();
+
+  // ---- phase B: group max / scan / carried weight / draw -------------------
+  const bool sys = a.systematic != 0;
+  if (!BLOCKPATH) {
+    // r <= 64: a group is a segment of r lanes
+    const uint32_t seg = lane & ~(r - 1u);
+    const uint32_t q = lane & (r - 1u);
+    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
+      const uint32_t c = (task << (6 - log2r)) + (lane >> log2r);
+      const T l = scl[c * P + q];
+      T m = l;
+      for (uint32_t s = 1; s < r; s <<= 1) m = fmaxT(m, __shfl_xor(m, (int)s, 64));
+      T cdf = fexp(l - m);
+      for (uint32_t s = 1; s < r; s <<= 1) {
+        const T o = __shfl_up(cdf, s, 64);
+        if (q >= s) cdf += o;
+      }
+      const T tot = __shfl(cdf, (int)(seg + r - 1u), 64);
+      const T u = scu[c * P + q];
+      const T u0 = __shfl(u, (int)seg, 64);
+      const T target = sys ? ((T)q + u0) * tot / (T)r : u * tot;
+      uint32_t pos = 0;
+      for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
+        const T v = __shfl(cdf, (int)(seg + pos + s - 1u), 64);
+        if (v <= target) pos += s;
+      }
+      sca[c * P + q] = (int)pos;
+      if (q == 0) colw[c] = m + flog(tot) - a.lnr;
+    }
+  } else {
+    // r > 64: 64-member chunks, chunk maxima and sums through LDS
+    const uint32_t lg_nch = log2r - 6;
+    const uint32_t nch = 1u << lg_nch;
+    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
+      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
+      const T m = wave_max(scl[c * P + (ch << 6) + lane]);
+      if (lane == 0) chm[task] = m;
+    }
+    __syncthreads();
+    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
+      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
+      T m = chm[c << lg_nch];
+      for (uint32_t i = 1; i < nch; ++i) m = fmaxT(m, chm[(c << lg_nch) + i]);
+      const uint32_t qq = (ch << 6) + lane;
+      const T cdf = wave_incl_scan(fexp(scl[c * P + qq] - m), lane);
+      scl[c * P + qq] = cdf;
+      if (lane == 63) chs[task] = cdf;
+      if (ch == 0 && lane == 0) colm[c] = m;
+    }
+    __syncthreads();
+    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
+      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
+      T offs = 0, tot = 0;
+      for (uint32_t i = 0; i < nch; ++i) {
+        if (i == ch) offs = tot;
+        tot += chs[(c << lg_nch) + i];
+      }
+      const uint32_t qq = (ch << 6) + lane;
+      scl[c * P + qq] += offs;
+      if (ch == 0 && lane == 0) {
+        coltot[c] = tot;
+        colw[c] = colm[c] + flog(tot) - a.lnr;
+      }
+    }
+    __syncthreads();
+    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
+      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
+      const uint32_t qq = (ch << 6) + lane;
+      const T tot = coltot[c];
+      const T u = scu[c * P + qq];
+      const T target = sys ? ((T)qq + scu[c * P]) * tot / (T)r : u * tot;
+      uint32_t pos = 0;
+      for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
+        if (scl[c * P + pos + s - 1u] <= target) pos += s;
+      }
+      sca[c * P + qq] = (int)pos;
+    }
+  }
+  __syncthreads();
+  // max of the new log-weights of this tile -> partial slot 4
+  if (wv == 0) {
+    T mm = -INFINITY;
+    for (uint32_t c = lane; c < C; c += 64) mm = fmaxT(mm, colw[c]);
+    mm = wave_max(mm);
+    if (lane == 0) __hip_atomic_store(&prt[4], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  // ---- phase C: gather, propagate, store -----------------------------------
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const uint32_t f0 = 2u * (tid + it * NT);
+    T xo[2][D], lwo[2];
+    uint64_t g0 = 0;
+    uint32_t ai[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      uint32_t q, c;
+      uint64_t gi;
+      tile_coords(geo, f0 + e, q, c, gi);
+      if (e == 0) g0 = gi;
+      const uint32_t pos = (uint32_t)sca[c * P + q];
+      T xh[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j) xh[j] = (j < d) ? xs[(size_t)j * E + (pos << log2C) + c] : (T)0;
+      Model<D, MK, T>::propagate(a.mp, xh, zr[2 * it + e], xo[e]);
+      lwo[e] = colw[c];
+      ai[e] = (uint32_t)((int64_t)gi + ((int64_t)pos - (int64_t)q) * ((int64_t)1 << a.log2R));
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + g0, xo[0][j], xo[1][j]);
+    Pair<T, T>::store(a.lw_out + g0, lwo[0], lwo[1]);
+    if (a.anc) {
+      a.anc[g0] = ai[0];
+      a.anc[g0 + 1] = ai[1];
+    }
+  }
+
+  // ---- tail: the last tile reduces every partial ---------------------------
+  // The partials were written with device-coherent stores; waiting for this
+  // thread's stores to complete before the barrier orders them before the
+  // ticket without an agent-scope fence (which would write back and
+  // invalidate the whole L2 of the XCD).
+  __shared__ uint32_t is_last;
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __builtin_amdgcn_s_waitcnt(0);
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);
+  __syncthreads();
+  if (tid == 0) {
+    const uint32_t prev =
+        __hip_atomic_fetch_add(&a.ctl->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    is_last = (prev == a.ntiles - 1u) ? 1u : 0u;
+  }
+  __syncthreads();
+  if (is_last) {
+    finalize_partials<D, T, NT>(fin_args(a), a.partials, a.ntiles, reinterpret_cast<double*>(smem),
+                                true, true);
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Global path, kernel 1: log-weights, tile max, tile inclusive CDF and
+// estimate partials. Every thread owns NLOC contiguous particles.
+// ---------------------------------------------------------------------------
+template <int D, int MK, typename T, typename S, int NT, int PPT>
+__global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
+  constexpr int NLOC = 2 * PPT;
+  constexpr int PS = partial_stride(D);
+  constexpr uint32_t E = 2u * NT * PPT;
+  __shared__ T red[(NT / 64) * PS];
+  __shared__ T wtot[NT / 64];
+  const int d = (int)a.d;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const uint32_t tile = blockIdx.x;
+  const uint64_t base = (uint64_t)tile * E + (uint64_t)tid * NLOC;
+  const uint64_t N = a.N;
+  T y[D], shift[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    y[j] = 0;
+    shift[j] = 0;
+    if (j < d) {
+      y[j] = a.y_dev ? a.y_dev[j] : a.y_val[j];
+      shift[j] = (T)a.ctl->shift[j];
+    }
+  }
+  T lr[NLOC], xr[NLOC][D], lwn[NLOC];
+  T tmax = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < NLOC; e += 2) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      xr[e][j] = xr[e + 1][j] = 0;
+      if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + base + e, xr[e][j], xr[e + 1][j]);
+    }
+    lwn[e] = lwn[e + 1] = 0;  // after a global resample every log-weight is 0
+    if (a.lw_nonzero) {
+      T w0, w1;
+      Pair<T, T>::load(a.lw_in + base + e, w0, w1);
+      const T off = (T)a.ctl->offset;
+      lwn[e] = w0 - off;
+      lwn[e + 1] = w1 - off;
+    }
+    lr[e] = lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y);
+    lr[e + 1] = lwn[e + 1] + Model<D, MK, T>::log_g(a.mp, xr[e + 1], y);
+    tmax = fmaxT(tmax, fmaxT(lr[e], lr[e + 1]));
+  }
+  const T mtile = block_max<T, NT>(tmax, red);
+  // inclusive CDF of e^{l - mtile} over the tile, in particle order
+  T w[NLOC];
+  T run = 0;
+#pragma unroll
+  for (int e = 0; e < NLOC; ++e) {
+    w[e] = fexp(lr[e] - mtile);
+    run += w[e];
+  }
+  const T incl = wave_incl_scan(run, lane);
+  if (lane == 63) wtot[wv] = incl;
+  __syncthreads();
+  T woff = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < NT / 64; ++i) {
+    if (i == wv) woff = tot;
+    tot += wtot[i];
+  }
+  T c = woff + incl - run;
+#pragma unroll
+  for (int e = 0; e < NLOC; ++e) {
+    c += w[e];
+    a.gcdf[base + e] = c;
+    if (((tid * NLOC + e) & 63) == 63) a.gcoarse[(base + e) >> 6] = c;
+  }
+  T* prt = a.partials + (size_t)tile * PS;
+  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, shift, d, mtile, red, prt);
+  __syncthreads();
+  if (tid == 0) {
+    prt[1] = tot;  // the tile's weight sum is the CDF total (same rounding as the CDF)
+    prt[4] = 0;
+  }
+}
+
+// Global path, kernel 2 (one block): tile prefix in FP64 and the finalize.
+template <int D, typename T, typename S, int NT>
+__global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* sd = reinterpret_cast<double*>(smem);
+  constexpr int PS = partial_stride(D);
+  const uint32_t nt = a.ntiles;
+  const int tid = threadIdx.x;
+  // global max of the tile maxima
+  double m = -INFINITY;
+  for (uint32_t b = tid; b < nt; b += NT) m = fmax(m, (double)a.partials[(size_t)b * PS]);
+  sd[tid] = m;
+  __syncthreads();
+  for (int s = NT / 2; s > 0; s >>= 1) {
+    if (tid < s) sd[tid] = fmax(sd[tid], sd[tid + s]);
+    __syncthreads();
+  }
+  const double M = sd[0];
+  __syncthreads();
+  // exclusive prefix of T_b = S_b e^{m_b - M}: contiguous chunks per thread
+  const uint32_t per = (nt + NT - 1) / NT;
+  const uint32_t b0 = tid * per, b1 = min(nt, b0 + per);
+  double loc = 0.0;
+  for (uint32_t b = b0; b < b1; ++b) {
+    const double e = exp((double)a.partials[(size_t)b * PS] - M);
+    a.gscale[b] = e;
+    loc += e * (double)a.partials[(size_t)b * PS + 1];
+  }
+  sd[tid] = loc;
+  __syncthreads();
+  // Hillis-Steele over thread totals (fixed order)
+  for (int s = 1; s < NT; s <<= 1) {
+    const double o = tid >= s ? sd[tid - s] : 0.0;
+    __syncthreads();
+    sd[tid] += o;
+    __syncthreads();
+  }
+  double run = sd[tid] - loc;
+  for (uint32_t b = b0; b < b1; ++b) {
+    a.gpre[b] = run;
+    run += a.gscale[b] * (double)a.partials[(size_t)b * PS + 1];
+  }
+  if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
+  __syncthreads();
+  finalize_partials<D, T, NT>(fin_args(a), a.partials, nt, sd, false, false);
+  if (tid == 0) a.ctl->offset = 0.0;  // every new log-weight is equal: renormalised to 0
+}
+
+// Global path, kernel 3: inverse-CDF draw over the whole population (tile
+// prefix, then the tile's coarse CDF, then 64 fine entries), gather from
+// HBM, propagate, store.
+template <int D, int MK, typename T, typename S, int NT, int PPT>
+__global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t tile_elems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  double* spre = reinterpret_cast<double*>(smem);
+  const uint32_t nt = a.ntiles;
+  const bool pre_in_lds = nt <= 4096u;
+  if (pre_in_lds) {
+    for (uint32_t b = threadIdx.x; b <= nt; b += NT) spre[b] = a.gpre[b];
+  }
+  __syncthreads();
+  const double* pre = pre_in_lds ? spre : a.gpre;
+  const int d = (int)a.d;
+  const uint64_t N = a.N;
+  const double total = a.gpre[nt];
+  const uint32_t tau = a.t + 1u;
+  const uint32_t lg_e = 31u - __clz(tile_elems);
+  const uint32_t ncoarse = tile_elems >> 6;
+  double u0sys = 0.0;
+  if (a.systematic) u0sys = word_uniform<double>(philox(0u, tau, 0u, a.sid, a.k0, a.k1).w0);
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const uint64_t p = ((uint64_t)blockIdx.x * PPT + it) * NT + threadIdx.x;
+    if (2 * p >= N) break;
+    T u[2], z[2][D], xo[2][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) z[0][j] = z[1][j] = 0;
+    pair_randoms<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, u[0], u[1], z[0], z[1]);
+    uint32_t anc[2];
+#pragma unroll
+    for (int e = 0; e < 2; ++e) {
+      const uint64_t i = 2 * p + e;
+      const double target = a.systematic ? ((double)i + u0sys) * total / (double)N
+                                         : (double)u[e] * total;
+      // tile: number of tile prefixes P_1..P_nt that are <= target
+      uint32_t b = 0;
+      for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
+        if (b + s <= nt && pre[b + s] <= target) b += s;
+      }
+      uint64_t a_idx;
+      if (b >= nt) {
+        a_idx = N - 1;
+      } else {
+        const T lt = (T)((target - pre[b]) / a.gscale[b]);
+        const T* co = a.gcoarse + (size_t)b * ncoarse;
+        uint32_t ch = 0;
+        for (uint32_t s = ncoarse >> 1; s >= 1u; s >>= 1)
+          if (co[ch + s - 1] <= lt) ch += s;
+        if (ch >= ncoarse) ch = ncoarse - 1;
+        const T* fine = a.gcdf + ((uint64_t)b << lg_e) + ((uint64_t)ch << 6);
+        uint32_t pos = 0;
+        for (uint32_t s = 32; s >= 1u; s >>= 1)
+          if (fine[pos + s - 1] <= lt) pos += s;
+        a_idx = ((uint64_t)b << lg_e) + ((uint64_t)ch << 6) + pos;
+      }
+      anc[e] = (uint32_t)a_idx;
+      T xh[D];
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        xh[j] = (j < d) ? Single<S, T>::load(a.x_in + (size_t)j * N + a_idx) : (T)0;
+      Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
+    }
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + 2 * p, xo[0][j], xo[1][j]);
+    if (a.anc) {
+      a.anc[2 * p] = anc[0];
+      a.anc[2 * p + 1] = anc[1];
+    }
+  }
+}
+
+}  // namespace pfk

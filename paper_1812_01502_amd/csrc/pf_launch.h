@@ -1,0 +1,160 @@
+// pf_launch.h - host-side dispatch from a launch request to a compiled
+// kernel instantiation. Each dtype translation unit (pf_kernels_*.hip)
+// instantiates PFK_DEFINE_LAUNCHER once.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "pf_kernels.h"
+
+namespace pfk {
+
+enum LaunchWhat : int {
+  LW_INIT = 0,
+  LW_STEP_TILE = 1,
+  LW_GLOBAL_WEIGHT = 2,
+  LW_GLOBAL_PREFIX = 3,
+  LW_GLOBAL_DRAW = 4
+};
+
+// What the runtime asks for.
+struct LaunchReq {
+  int what;
+  int D;         // compiled dimension (1, 2, 4, 8, 16)
+  int mk;        // ModelKind
+  int nt;        // threads per block
+  int ppt;       // particle pairs per thread
+  int blockpath; // tile kernels: 1 = r > 64
+  uint32_t grid;
+  size_t lds;    // dynamic LDS bytes
+  uint32_t tile_elems;  // global draw: particles per weight tile
+};
+
+// Pairs per thread of the butterfly wave path (256 threads) by dimension:
+// keeps the registers held across the step (states, normals) bounded.
+constexpr int ppt_wave(int D) { return D <= 2 ? 4 : (D <= 8 ? 2 : 1); }
+// Pairs per thread of the global weight kernel (256 threads).
+constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
+constexpr int kDrawPPT = 4;
+
+template <typename K> static hipError_t ensure_lds(K* kernel, size_t bytes) {
+  if (bytes <= 65536) return hipSuccess;
+  return hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                             hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
+}
+
+template <int D, int MK, typename T, typename S>
+static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hipStream_t st) {
+  switch (rq.what) {
+    case LW_INIT: {
+      hipLaunchKernelGGL((pf_init_kernel<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
+      return hipGetLastError();
+    }
+    case LW_STEP_TILE: {
+      if (!rq.blockpath) {
+        if (rq.nt == 256 && rq.ppt == ppt_wave(D)) {
+          auto k = pf_step_tile<D, MK, T, S, 256, ppt_wave(D), false>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+          return hipGetLastError();
+        }
+        if (rq.nt == 64 && rq.ppt == 1) {
+          auto k = pf_step_tile<D, MK, T, S, 64, 1, false>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(64), rq.lds, st, a);
+          return hipGetLastError();
+        }
+        return hipErrorInvalidValue;
+      }
+      if (rq.nt == 256 && rq.ppt == 1) {
+        auto k = pf_step_tile<D, MK, T, S, 256, 1, true>;
+        hipError_t e = ensure_lds(k, rq.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+        return hipGetLastError();
+      }
+      if (rq.nt == 1024 && rq.ppt == 1) {
+        auto k = pf_step_tile<D, MK, T, S, 1024, 1, true>;
+        hipError_t e = ensure_lds(k, rq.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+        return hipGetLastError();
+      }
+      if constexpr (D <= 4) {
+        if (rq.nt == 1024 && rq.ppt == 2) {
+          auto k = pf_step_tile<D, MK, T, S, 1024, 2, true>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+          return hipGetLastError();
+        }
+        if (rq.nt == 1024 && rq.ppt == 4) {
+          auto k = pf_step_tile<D, MK, T, S, 1024, 4, true>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+          return hipGetLastError();
+        }
+      }
+      return hipErrorInvalidValue;
+    }
+    case LW_GLOBAL_WEIGHT: {
+      if (rq.nt == 256 && rq.ppt == ppt_gweight(D)) {
+        hipLaunchKernelGGL((pf_global_weight<D, MK, T, S, 256, ppt_gweight(D)>), dim3(rq.grid),
+                           dim3(256), 0, st, a);
+        return hipGetLastError();
+      }
+      if (rq.nt == 64 && rq.ppt == 1) {
+        hipLaunchKernelGGL((pf_global_weight<D, MK, T, S, 64, 1>), dim3(rq.grid), dim3(64), 0, st, a);
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
+    }
+    case LW_GLOBAL_PREFIX: {
+      auto k = pf_global_prefix<D, T, S, 256>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(1), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    case LW_GLOBAL_DRAW: {
+      auto k = pf_global_draw<D, MK, T, S, 256, kDrawPPT>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a, rq.tile_elems);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+template <typename T, typename S>
+static hipError_t launch_any(const LaunchReq& rq, const void* args, hipStream_t st) {
+  const StepArgs<T, S>& a = *reinterpret_cast<const StepArgs<T, S>*>(args);
+  if (rq.mk == MK_SV) {
+    if (rq.D != 1) return hipErrorInvalidValue;
+    return launch_model<1, MK_SV, T, S>(rq, a, st);
+  }
+#define PFK_DIMS(MKV)                                                \
+  switch (rq.D) {                                                    \
+    case 1: return launch_model<1, MKV, T, S>(rq, a, st);            \
+    case 2: return launch_model<2, MKV, T, S>(rq, a, st);            \
+    case 4: return launch_model<4, MKV, T, S>(rq, a, st);            \
+    case 8: return launch_model<8, MKV, T, S>(rq, a, st);            \
+    case 16: return launch_model<16, MKV, T, S>(rq, a, st);          \
+    default: return hipErrorInvalidValue;                            \
+  }
+  if (rq.mk == MK_LG_DENSE) { PFK_DIMS(MK_LG_DENSE) }
+  if (rq.mk == MK_LG_DIAG) { PFK_DIMS(MK_LG_DIAG) }
+#undef PFK_DIMS
+  return hipErrorInvalidValue;
+}
+
+// Entry points of the three dtype translation units.
+hipError_t launch_f32(const LaunchReq& rq, const void* args, hipStream_t st);
+hipError_t launch_bf16(const LaunchReq& rq, const void* args, hipStream_t st);
+hipError_t launch_f64(const LaunchReq& rq, const void* args, hipStream_t st);
+
+}  // namespace pfk

@@ -1,0 +1,795 @@
+// pf_runtime.hip - the C-ABI of include/pf.h: handle, stage planner, device
+// buffers, kernel launches, state access and error handling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/pf.h"
+#include "pf_launch.h"
+
+using namespace pfk;
+
+namespace {
+
+thread_local std::string g_create_error;
+
+struct StagePlan {
+  uint32_t r, log2r;
+  uint64_t R;
+  uint32_t log2R;
+  // tile kernel geometry
+  int blockpath, nt, ppt;
+  uint32_t C, log2C, pad, ntiles;
+  size_t lds;
+};
+
+bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
+uint32_t ilog2(uint64_t v) {
+  uint32_t l = 0;
+  while ((1ull << l) < v) ++l;
+  return l;
+}
+
+}  // namespace
+
+struct pf_handle {
+  int kind = 0, d = 0, D = 1, mk = 0;
+  int dtype = PF_DTYPE_F32;
+  int resampler = PF_RESAMPLE_MULTINOMIAL;
+  uint64_t N = 0, radix = 0;
+  uint64_t seed = 0;
+  uint32_t sid = 0;
+  bool global = false;
+  std::vector<StagePlan> stages;
+  hipStream_t stream = nullptr;
+  size_t tsz = 4, ssz = 4;  // compute / storage element sizes
+  void* x[2] = {nullptr, nullptr};
+  void* lw[2] = {nullptr, nullptr};
+  int cur = 0;
+  void* mp = nullptr;        // ModelParams<T>
+  void* partials = nullptr;
+  Ctl* ctl = nullptr;
+  pf_estimate_t* hist = nullptr;
+  uint32_t hist_cap = 1;
+  uint32_t* anc = nullptr;
+  void* gcdf = nullptr;
+  void* gcoarse = nullptr;
+  double* gpre = nullptr;
+  double* gscale = nullptr;
+  uint32_t g_tile = 0, g_ntiles = 0, g_nt = 256, g_ppt = 1;
+  uint64_t t = 0;
+  bool lw_zero = true;       // every log-weight is 0 (global path bookkeeping)
+  uint64_t bytes = 0;
+  pf_status sticky = PF_OK;
+  std::string err;
+  std::vector<void*> allocs;
+};
+
+namespace {
+
+pf_status fail(pf_handle* h, pf_status s, const std::string& msg) {
+  if (h) {
+    h->err = msg;
+    if (s == PF_E_HIP) h->sticky = PF_E_STATE;
+  } else {
+    g_create_error = msg;
+  }
+  return s;
+}
+
+pf_status hip_fail(pf_handle* h, hipError_t e, const char* what) {
+  std::string m = std::string(what) + ": " + hipGetErrorString(e);
+  return fail(h, PF_E_HIP, m);
+}
+
+pf_status dalloc(pf_handle* h, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  hipError_t e = hipMalloc(p, bytes);
+  if (e != hipSuccess) {
+    *p = nullptr;
+    (void)hipGetLastError();
+    return fail(h, PF_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
+  }
+  h->allocs.push_back(*p);
+  h->bytes += bytes;
+  return PF_OK;
+}
+
+bool finite_all(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+// Inverse of a lower-triangular matrix (row-major d x d), FP64.
+void lower_inverse(const double* L, int d, double* out) {
+  for (int i = 0; i < d * d; ++i) out[i] = 0.0;
+  for (int j = 0; j < d; ++j) {
+    out[j * d + j] = 1.0 / L[j * d + j];
+    for (int i = j + 1; i < d; ++i) {
+      double s = 0.0;
+      for (int k = j; k < i; ++k) s += L[i * d + k] * out[k * d + j];
+      out[i * d + j] = -s / L[i * d + i];
+    }
+  }
+}
+
+template <typename T>
+void fill_params(const pf_model* m, int d, ModelParams<T>* P, int* mk_out) {
+  std::memset(P, 0, sizeof(*P));
+  if (m->kind == PF_MODEL_SV) {
+    P->phi = (T)m->phi;
+    P->sigma = (T)m->sigma;
+    P->inv2b2 = (T)(1.0 / (2.0 * m->beta * m->beta));
+    P->sd0 = (T)(m->sigma / std::sqrt(1.0 - m->phi * m->phi));
+    P->lconst = (T)(-0.5 * std::log(2.0 * M_PI * m->beta * m->beta));
+    *mk_out = MK_SV;
+    return;
+  }
+  std::vector<double> Li(d * d);
+  lower_inverse(m->R_chol, d, Li.data());
+  double logdet = 0.0;
+  for (int j = 0; j < d; ++j) logdet += std::log(m->R_chol[j * d + j]);
+  P->lconst = (T)(-logdet - 0.5 * d * std::log(2.0 * M_PI));
+  bool diag = true;
+  for (int i = 0; i < d; ++i)
+    for (int j = 0; j < d; ++j) {
+      const double hij = m->H[i * d + j];
+      if (hij != (i == j ? 1.0 : 0.0)) diag = false;
+      if (i != j && (m->R_chol[i * d + j] != 0.0 || m->Q_chol[i * d + j] != 0.0)) diag = false;
+    }
+  for (int i = 0; i < d; ++i) {
+    P->m0[i] = (T)m->m0[i];
+    P->qd[i] = (T)m->Q_chol[i * d + i];
+    P->lid[i] = (T)Li[i * d + i];
+    for (int j = 0; j < d; ++j) {
+      P->A[i * kMaxDim + j] = (T)m->A[i * d + j];
+      P->H[i * kMaxDim + j] = (T)m->H[i * d + j];
+      if (j <= i) {
+        P->Lq[i * kMaxDim + j] = (T)m->Q_chol[i * d + j];
+        P->Li[i * kMaxDim + j] = (T)Li[i * d + j];
+        P->L0[i * kMaxDim + j] = (T)m->P0_chol[i * d + j];
+      }
+    }
+  }
+  *mk_out = diag ? MK_LG_DIAG : MK_LG_DENSE;
+}
+
+hipError_t launch(pf_handle* h, const LaunchReq& rq, const void* args) {
+  switch (h->dtype) {
+    case PF_DTYPE_F32: return launch_f32(rq, args, h->stream);
+    case PF_DTYPE_BF16: return launch_bf16(rq, args, h->stream);
+    default: return launch_f64(rq, args, h->stream);
+  }
+}
+
+// Bank-conflict cost of the LDS pad for the per-group scalar arrays
+// (layout [column][r + pad]): phase-A/C accesses by consecutive pairs and
+// phase-B accesses by group lanes, evaluated for 32 and 64 banks.
+uint32_t choose_pad(uint32_t r, uint32_t C, uint32_t log2R, int nt) {
+  const uint32_t log2r = ilog2(r), log2C = ilog2(C);
+  const bool wide = log2R >= log2C;
+  auto coords = [&](uint32_t f, uint32_t& q, uint32_t& c) {
+    if (wide) {
+      q = f >> log2C;
+      c = f & (C - 1);
+    } else {
+      const uint32_t sh = log2r + log2R;
+      const uint32_t hb = f >> sh, rem = f & ((1u << sh) - 1);
+      q = rem >> log2R;
+      c = (hb << log2R) | (rem & ((1u << log2R) - 1));
+    }
+  };
+  uint32_t best = 0;
+  double best_cost = 1e30;
+  const uint32_t cands[] = {0, 1, 2, 3, 4, 5, 8};
+  for (uint32_t pad : cands) {
+    const uint32_t P = r + pad;
+    double cost = 0;
+    for (int banks : {32, 64}) {
+      auto degree = [&](const std::vector<uint32_t>& addr, int lanes_per_cycle) {
+        double tot = 0;
+        for (size_t g = 0; g < addr.size(); g += lanes_per_cycle) {
+          std::vector<std::vector<uint32_t>> b(banks);
+          int mx = 0;
+          for (size_t i = g; i < g + lanes_per_cycle && i < addr.size(); ++i) {
+            auto& v = b[addr[i] % banks];
+            bool seen = false;
+            for (uint32_t a : v) seen |= (a == addr[i]);
+            if (!seen) v.push_back(addr[i]);
+            mx = std::max<int>(mx, (int)v.size());
+          }
+          tot += mx;
+        }
+        return tot;
+      };
+      const int lpc = banks == 32 ? 32 : 64;
+      for (int e = 0; e < 2; ++e) {
+        std::vector<uint32_t> addr;
+        for (int l = 0; l < 64 && l < nt; ++l) {
+          uint32_t q, c;
+          coords(2u * l + e, q, c);
+          addr.push_back(c * P + q);
+        }
+        cost += degree(addr, lpc);
+      }
+      if (r <= 64) {
+        std::vector<uint32_t> addr;
+        for (uint32_t l = 0; l < 64; ++l) addr.push_back((l >> log2r) * P + (l & (r - 1)));
+        cost += 2 * degree(addr, lpc);
+      } else {
+        std::vector<uint32_t> addr;
+        for (uint32_t l = 0; l < 64; ++l) addr.push_back(l);
+        cost += 2 * degree(addr, lpc);
+      }
+    }
+    cost += 0.01 * pad;  // prefer the smaller pad on ties
+    if (cost < best_cost) {
+      best_cost = cost;
+      best = pad;
+    }
+  }
+  return best;
+}
+
+template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>& a) {
+  std::memset(&a, 0, sizeof(a));
+  a.x_in = reinterpret_cast<const S*>(h->x[h->cur]);
+  a.x_out = reinterpret_cast<S*>(h->x[h->cur ^ 1]);
+  a.lw_in = reinterpret_cast<const T*>(h->lw[h->cur]);
+  a.lw_out = reinterpret_cast<T*>(h->lw[h->cur ^ 1]);
+  a.anc = h->anc;
+  a.mp = reinterpret_cast<const ModelParams<T>*>(h->mp);
+  a.partials = reinterpret_cast<T*>(h->partials);
+  a.ctl = h->ctl;
+  a.hist = h->hist;
+  a.hist_cap = h->hist_cap;
+  a.d = (uint32_t)h->d;
+  a.N = h->N;
+  a.k0 = (uint32_t)(h->seed & 0xFFFFFFFFu);
+  a.k1 = (uint32_t)(h->seed >> 32);
+  a.sid = h->sid;
+  a.systematic = h->resampler == PF_RESAMPLE_SYSTEMATIC ? 1 : 0;
+  a.gcdf = reinterpret_cast<T*>(h->gcdf);
+  a.gcoarse = reinterpret_cast<T*>(h->gcoarse);
+  a.gpre = h->gpre;
+  a.gscale = h->gscale;
+}
+
+template <typename T, typename S>
+pf_status run_init(pf_handle* h) {
+  StepArgs<T, S> a;
+  fill_common<T, S>(h, a);
+  // the initial cloud goes to the current buffer
+  a.x_out = reinterpret_cast<S*>(h->x[h->cur]);
+  a.lw_out = reinterpret_cast<T*>(h->lw[h->cur]);
+  LaunchReq rq{};
+  rq.what = LW_INIT;
+  rq.D = h->D;
+  rq.mk = h->mk;
+  rq.nt = 256;
+  const uint64_t npair = h->N / 2;
+  uint64_t g = (npair + 255) / 256;
+  rq.grid = (uint32_t)(g > 65536 ? 65536 : g);
+  hipError_t e = launch(h, rq, &a);
+  if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
+  h->t = 0;
+  h->lw_zero = true;
+  return PF_OK;
+}
+
+// One time step; y either by value (y_host) or in device memory (y_dev).
+template <typename T, typename S>
+pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
+  StepArgs<T, S> a;
+  fill_common<T, S>(h, a);
+  if (y_dev) {
+    a.y_dev = reinterpret_cast<const T*>(y_dev);
+  } else {
+    for (int j = 0; j < h->d; ++j) a.y_val[j] = (T)y_host[j];
+  }
+  const uint32_t S_ = (uint32_t)h->stages.size();
+  const uint32_t k = (uint32_t)(h->t % S_);
+  const StagePlan& sp = h->stages[k];
+  a.t = (uint32_t)h->t;
+  a.k = k;
+  a.radix = sp.r;
+  a.log2r = sp.log2r;
+  a.log2R = sp.log2R;
+  a.lnr = (T)std::log((double)sp.r);
+  hipError_t e;
+  if (!h->global) {
+    a.log2C = sp.log2C;
+    a.pad = sp.pad;
+    a.ntiles = sp.ntiles;
+    LaunchReq rq{};
+    rq.what = LW_STEP_TILE;
+    rq.D = h->D;
+    rq.mk = h->mk;
+    rq.nt = sp.nt;
+    rq.ppt = sp.ppt;
+    rq.blockpath = sp.blockpath;
+    rq.grid = sp.ntiles;
+    rq.lds = sp.lds;
+    e = launch(h, rq, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
+  } else {
+    a.ntiles = h->g_ntiles;
+    a.lw_nonzero = h->lw_zero ? 0 : 1;
+    LaunchReq rq{};
+    rq.D = h->D;
+    rq.mk = h->mk;
+    rq.what = LW_GLOBAL_WEIGHT;
+    rq.nt = (int)h->g_nt;
+    rq.ppt = (int)h->g_ppt;
+    rq.grid = h->g_ntiles;
+    e = launch(h, rq, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "global weight launch");
+    rq.what = LW_GLOBAL_PREFIX;
+    rq.nt = 256;
+    rq.grid = 1;
+    rq.lds = std::max<size_t>(256 * 8, (size_t)4 * partial_stride(h->D) * 8);
+    e = launch(h, rq, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "global prefix launch");
+    rq.what = LW_GLOBAL_DRAW;
+    rq.nt = 256;
+    rq.ppt = kDrawPPT;
+    const uint64_t pairs_per_block = 256ull * kDrawPPT;
+    rq.grid = (uint32_t)((h->N / 2 + pairs_per_block - 1) / pairs_per_block);
+    rq.lds = h->g_ntiles <= 4096 ? (size_t)(h->g_ntiles + 1) * 8 : 16;
+    rq.tile_elems = h->g_tile;
+    e = launch(h, rq, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "global draw launch");
+  }
+  // the global path does not store log-weights: after it every one is 0
+  h->cur ^= 1;
+  h->lw_zero = h->global;
+  h->t += 1;
+  return PF_OK;
+}
+
+pf_status do_init(pf_handle* h) {
+  switch (h->dtype) {
+    case PF_DTYPE_F32: return run_init<float, float>(h);
+    case PF_DTYPE_BF16: return run_init<float, bf16>(h);
+    default: return run_init<double, double>(h);
+  }
+}
+
+pf_status do_step(pf_handle* h, const double* y_host, const void* y_dev) {
+  switch (h->dtype) {
+    case PF_DTYPE_F32: return run_step<float, float>(h, y_host, y_dev);
+    case PF_DTYPE_BF16: return run_step<float, bf16>(h, y_host, y_dev);
+    default: return run_step<double, double>(h, y_host, y_dev);
+  }
+}
+
+pf_status plan_stages(pf_handle* h) {
+  const uint64_t N = h->N;
+  const uint32_t n = ilog2(N);
+  if (h->radix >= N) {
+    h->global = true;
+    StagePlan sp{};
+    sp.r = (uint32_t)std::min<uint64_t>(N, 0xFFFFFFFFu);
+    sp.log2r = n;
+    sp.R = 1;
+    sp.log2R = 0;
+    h->stages.push_back(sp);
+    // weight tiles
+    uint32_t nt = 256, ppt = (uint32_t)ppt_gweight(h->D);
+    uint64_t E = 2ull * nt * ppt;
+    if (E > N) {
+      nt = 64;
+      ppt = 1;
+      E = 128;
+    }
+    if (E > N) return fail(h, PF_E_UNSUPPORTED, "N must be at least 128 on the device");
+    h->g_nt = nt;
+    h->g_ppt = ppt;
+    h->g_tile = (uint32_t)E;
+    h->g_ntiles = (uint32_t)(N / E);
+    return PF_OK;
+  }
+  const uint32_t b = ilog2(h->radix);
+  const uint32_t S = (n + b - 1) / b;
+  const uint32_t last = n - (S - 1) * b;
+  uint64_t R = 1;
+  for (uint32_t k = 0; k < S; ++k) {
+    StagePlan sp{};
+    sp.log2r = (k + 1 < S) ? b : last;
+    sp.r = 1u << sp.log2r;
+    sp.R = R;
+    sp.log2R = ilog2(R);
+    R *= sp.r;
+    uint32_t E;
+    if (sp.r <= 64) {
+      sp.blockpath = 0;
+      sp.nt = 256;
+      sp.ppt = ppt_wave(h->D);
+      E = 2u * sp.nt * sp.ppt;
+      if (E > N) {
+        sp.nt = 64;
+        sp.ppt = 1;
+        E = 128;
+      }
+    } else {
+      sp.blockpath = 1;
+      if (sp.r <= 1024 && N >= 2048) {
+        sp.nt = 1024;
+        sp.ppt = 1;
+      } else if (sp.r <= 256) {
+        sp.nt = 256;
+        sp.ppt = 1;
+      } else if (sp.r == 2048 && h->D <= 4) {
+        sp.nt = 1024;
+        sp.ppt = 2;
+      } else if (sp.r == 4096 && h->D <= 4) {
+        sp.nt = 1024;
+        sp.ppt = 4;
+      } else {
+        return fail(h, PF_E_UNSUPPORTED,
+                    "stage radix " + std::to_string(sp.r) + " is not supported for d = " +
+                        std::to_string(h->d) + " (use r <= 1024, or r >= N)");
+      }
+      E = 2u * sp.nt * sp.ppt;
+    }
+    if (E > N || E < 2u * sp.r)
+      return fail(h, PF_E_UNSUPPORTED, "N = " + std::to_string(N) + " is too small for a tile of radix " +
+                                           std::to_string(sp.r));
+    sp.C = E / sp.r;
+    sp.log2C = ilog2(sp.C);
+    sp.ntiles = (uint32_t)(N / E);
+    sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
+    sp.lds = tile_lds_bytes(h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0);
+    if (sp.lds > 160 * 1024)
+      return fail(h, PF_E_UNSUPPORTED, "tile of radix " + std::to_string(sp.r) + " needs " +
+                                           std::to_string(sp.lds) + " bytes of LDS (> 160 KiB)");
+    h->stages.push_back(sp);
+  }
+  return PF_OK;
+}
+
+void release(pf_handle* h) {
+  for (void* p : h->allocs) (void)hipFree(p);
+  h->allocs.clear();
+}
+
+bool poisoned(pf_handle* h) { return h->sticky != PF_OK; }
+
+}  // namespace
+
+extern "C" {
+
+const char* pf_status_string(pf_status s) {
+  switch (s) {
+    case PF_OK: return "ok";
+    case PF_E_INVALID: return "invalid argument";
+    case PF_E_UNSUPPORTED: return "unsupported";
+    case PF_E_OOM: return "out of device memory";
+    case PF_E_HIP: return "HIP runtime error";
+    case PF_E_NUMERIC: return "non-finite value";
+    case PF_E_STATE: return "handle in error state";
+  }
+  return "unknown status";
+}
+
+const char* pf_last_error(const pf_handle* h) {
+  if (!h) return g_create_error.c_str();
+  return h->err.c_str();
+}
+
+pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_stream, pf_handle** out) {
+  g_create_error.clear();
+  if (!out) return fail(nullptr, PF_E_INVALID, "out is NULL");
+  *out = nullptr;
+  if (!model || !cfg) return fail(nullptr, PF_E_INVALID, "model or config is NULL");
+  const int d = model->d;
+  if (model->kind != PF_MODEL_LG && model->kind != PF_MODEL_SV)
+    return fail(nullptr, PF_E_INVALID, "unknown model kind");
+  if (d < 1 || d > PF_MAX_DIM) return fail(nullptr, PF_E_INVALID, "d must be in [1, 16]");
+  if (model->kind == PF_MODEL_SV) {
+    if (d != 1) return fail(nullptr, PF_E_INVALID, "the SV model has d = 1");
+    if (!(std::fabs(model->phi) < 1.0) || !(model->sigma > 0.0) || !(model->beta > 0.0) ||
+        !std::isfinite(model->sigma) || !std::isfinite(model->beta))
+      return fail(nullptr, PF_E_INVALID, "SV parameters need |phi| < 1, sigma > 0, beta > 0");
+  } else {
+    const double* ms[] = {model->A, model->Q_chol, model->H, model->R_chol, model->P0_chol};
+    for (const double* m : ms)
+      if (!m || !finite_all(m, (size_t)d * d)) return fail(nullptr, PF_E_INVALID, "LG matrix NULL or non-finite");
+    if (!model->m0 || !finite_all(model->m0, d)) return fail(nullptr, PF_E_INVALID, "m0 NULL or non-finite");
+    const double* tri[] = {model->Q_chol, model->R_chol, model->P0_chol};
+    for (const double* L : tri)
+      for (int i = 0; i < d; ++i) {
+        if (!(L[i * d + i] > 0.0)) return fail(nullptr, PF_E_INVALID, "Cholesky factor needs a positive diagonal");
+        for (int j = i + 1; j < d; ++j)
+          if (L[i * d + j] != 0.0) return fail(nullptr, PF_E_INVALID, "Cholesky factor must be lower-triangular");
+      }
+  }
+  const uint64_t N = cfg->n_particles;
+  if (!is_pow2(N) || N < 2 || N > (1ull << 30))
+    return fail(nullptr, PF_E_INVALID, "n_particles must be a power of two in [2, 2^30]");
+  if (!is_pow2(cfg->radix) || cfg->radix < 2)
+    return fail(nullptr, PF_E_INVALID, "radix must be a power of two >= 2");
+  if (cfg->resampler != PF_RESAMPLE_MULTINOMIAL && cfg->resampler != PF_RESAMPLE_SYSTEMATIC)
+    return fail(nullptr, PF_E_INVALID, "unknown resampler");
+  if (cfg->state_dtype != PF_DTYPE_F32 && cfg->state_dtype != PF_DTYPE_BF16 &&
+      cfg->state_dtype != PF_DTYPE_F64)
+    return fail(nullptr, PF_E_INVALID, "unknown state dtype");
+
+  pf_handle* h = new (std::nothrow) pf_handle();
+  if (!h) return fail(nullptr, PF_E_OOM, "host allocation failed");
+  h->kind = model->kind;
+  h->d = d;
+  h->D = d <= 1 ? 1 : d <= 2 ? 2 : d <= 4 ? 4 : d <= 8 ? 8 : 16;
+  h->dtype = cfg->state_dtype;
+  h->resampler = cfg->resampler;
+  h->N = N;
+  h->radix = cfg->radix;
+  h->seed = cfg->seed;
+  h->sid = cfg->stream_id;
+  h->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  h->tsz = h->dtype == PF_DTYPE_F64 ? 8 : 4;
+  h->ssz = h->dtype == PF_DTYPE_F64 ? 8 : (h->dtype == PF_DTYPE_BF16 ? 2 : 4);
+  h->hist_cap = cfg->history ? cfg->history : 1;
+
+  auto bail = [&](pf_status s) {
+    g_create_error = h->err;
+    release(h);
+    delete h;
+    return s;
+  };
+  pf_status s = plan_stages(h);
+  if (s != PF_OK) return bail(s);
+
+  // model parameters
+  int mk = 0;
+  if (h->dtype == PF_DTYPE_F64) {
+    ModelParams<double> P;
+    fill_params<double>(model, d, &P, &mk);
+    if ((s = dalloc(h, &h->mp, sizeof(P))) != PF_OK) return bail(s);
+    hipError_t e = hipMemcpy(h->mp, &P, sizeof(P), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(h, e, "model upload"));
+  } else {
+    ModelParams<float> P;
+    fill_params<float>(model, d, &P, &mk);
+    if ((s = dalloc(h, &h->mp, sizeof(P))) != PF_OK) return bail(s);
+    hipError_t e = hipMemcpy(h->mp, &P, sizeof(P), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(h, e, "model upload"));
+  }
+  h->mk = mk;
+
+  // buffers
+  for (int i = 0; i < 2; ++i) {
+    if ((s = dalloc(h, &h->x[i], (size_t)d * N * h->ssz)) != PF_OK) return bail(s);
+    if ((s = dalloc(h, &h->lw[i], (size_t)N * h->tsz)) != PF_OK) return bail(s);
+  }
+  uint32_t max_tiles = h->global ? h->g_ntiles : 0;
+  for (auto& sp : h->stages) max_tiles = std::max(max_tiles, sp.ntiles);
+  if ((s = dalloc(h, &h->partials, (size_t)max_tiles * partial_stride(h->D) * h->tsz)) != PF_OK) return bail(s);
+  void* p = nullptr;
+  if ((s = dalloc(h, &p, sizeof(Ctl))) != PF_OK) return bail(s);
+  h->ctl = reinterpret_cast<Ctl*>(p);
+  if ((s = dalloc(h, &p, sizeof(pf_estimate_t) * h->hist_cap)) != PF_OK) return bail(s);
+  h->hist = reinterpret_cast<pf_estimate_t*>(p);
+  {
+    hipError_t e = hipMemset(h->hist, 0, sizeof(pf_estimate_t) * h->hist_cap);
+    if (e != hipSuccess) return bail(hip_fail(h, e, "history clear"));
+  }
+  if (cfg->keep_ancestors) {
+    if ((s = dalloc(h, &p, (size_t)N * 4)) != PF_OK) return bail(s);
+    h->anc = reinterpret_cast<uint32_t*>(p);
+  }
+  if (h->global) {
+    if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz)) != PF_OK) return bail(s);
+    if ((s = dalloc(h, &h->gcoarse, (size_t)(N / 64 + 1) * h->tsz)) != PF_OK) return bail(s);
+    if ((s = dalloc(h, &p, (size_t)(h->g_ntiles + 1) * 8)) != PF_OK) return bail(s);
+    h->gpre = reinterpret_cast<double*>(p);
+    if ((s = dalloc(h, &p, (size_t)h->g_ntiles * 8)) != PF_OK) return bail(s);
+    h->gscale = reinterpret_cast<double*>(p);
+  }
+  s = do_init(h);
+  if (s != PF_OK) return bail(s);
+  *out = h;
+  return PF_OK;
+}
+
+pf_status pf_destroy(pf_handle* h) {
+  if (!h) return PF_OK;
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  else (void)hipDeviceSynchronize();
+  release(h);
+  delete h;
+  return PF_OK;
+}
+
+pf_status pf_reset(pf_handle* h) {
+  if (!h) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  h->cur = 0;
+  return do_init(h);
+}
+
+pf_status pf_step(pf_handle* h, const double* y_host) {
+  if (!h) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  if (!y_host) return fail(h, PF_E_INVALID, "y is NULL");
+  if (!finite_all(y_host, h->d)) return fail(h, PF_E_NUMERIC, "non-finite observation");
+  return do_step(h, y_host, nullptr);
+}
+
+pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_stride, int32_t use_graph) {
+  if (!h) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  if (!y_dev) return fail(h, PF_E_INVALID, "y_dev is NULL");
+  if (y_stride < (uint64_t)h->d) return fail(h, PF_E_INVALID, "y_stride < d");
+  if (n_steps == 0) return PF_OK;
+  const char* yb = reinterpret_cast<const char*>(y_dev);
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  if (use_graph) {
+    if (!h->stream) return fail(h, PF_E_INVALID, "graph capture needs a non-default stream");
+    hipError_t e = hipStreamBeginCapture(h->stream, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
+  }
+  const uint64_t t0 = h->t;
+  const int cur0 = h->cur;
+  void* lw0[2] = {h->lw[0], h->lw[1]};
+  pf_status st = PF_OK;
+  for (uint32_t j = 0; j < n_steps && st == PF_OK; ++j)
+    st = do_step(h, nullptr, yb + (size_t)j * y_stride * h->tsz);
+  if (use_graph) {
+    hipError_t e = hipStreamEndCapture(h->stream, &graph);
+    if (st != PF_OK) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st;
+    }
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
+    e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      return hip_fail(h, e, "hipGraphInstantiate");
+    }
+    e = hipGraphLaunch(exec, h->stream);
+    (void)hipGraphExecDestroy(exec);
+    (void)hipGraphDestroy(graph);
+    if (e != hipSuccess) return hip_fail(h, e, "hipGraphLaunch");
+    (void)t0;
+    (void)cur0;
+    (void)lw0;
+  }
+  return st;
+}
+
+pf_status pf_sync(pf_handle* h) {
+  if (!h) return PF_E_INVALID;
+  hipError_t e = h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize();
+  if (e != hipSuccess) return hip_fail(h, e, "synchronize");
+  return PF_OK;
+}
+
+pf_status pf_estimate(pf_handle* h, pf_estimate_t* out) {
+  if (!h || !out) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  if (h->t == 0) return fail(h, PF_E_STATE, "no step has run");
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  const uint64_t slot = (h->t - 1) % h->hist_cap;
+  hipError_t e = hipMemcpy(out, h->hist + slot, sizeof(*out), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "estimate copy");
+  return PF_OK;
+}
+
+pf_status pf_history(pf_handle* h, pf_estimate_t* out, uint32_t n_max, uint32_t* n_out) {
+  if (!h || !out || !n_out) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  uint64_t n = std::min<uint64_t>(h->t, h->hist_cap);
+  n = std::min<uint64_t>(n, n_max);
+  std::vector<pf_estimate_t> all(h->hist_cap);
+  hipError_t e = hipMemcpy(all.data(), h->hist, sizeof(pf_estimate_t) * h->hist_cap, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "history copy");
+  for (uint64_t i = 0; i < n; ++i) {
+    const uint64_t t = h->t - n + i;
+    out[i] = all[t % h->hist_cap];
+  }
+  *n_out = (uint32_t)n;
+  return PF_OK;
+}
+
+pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_out, double* log_norm) {
+  if (!h) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  hipError_t e;
+  if (x_host) {
+    e = hipMemcpy(x_host, h->x[h->cur], (size_t)h->d * h->N * h->ssz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "state copy");
+  }
+  Ctl c;
+  e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "control copy");
+  if (logw_host && h->lw_zero) {
+    std::memset(logw_host, 0, (size_t)h->N * h->tsz);
+  } else if (logw_host) {
+    e = hipMemcpy(logw_host, h->lw[h->cur], (size_t)h->N * h->tsz, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "log-weight copy");
+    // stored log-weights are normalised by the offset the next step would subtract
+    if (h->tsz == 8) {
+      double* w = reinterpret_cast<double*>(logw_host);
+      for (uint64_t i = 0; i < h->N; ++i) w[i] -= c.offset;
+    } else {
+      float* w = reinterpret_cast<float*>(logw_host);
+      const float o = (float)c.offset;
+      for (uint64_t i = 0; i < h->N; ++i) w[i] -= o;
+    }
+  }
+  if (t_out) *t_out = (uint32_t)h->t;
+  if (log_norm) *log_norm = c.log_norm;
+  return PF_OK;
+}
+
+pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, uint32_t t, double log_norm) {
+  if (!h || !x_host) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  hipError_t e = hipMemcpy(h->x[h->cur], x_host, (size_t)h->d * h->N * h->ssz, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "state upload");
+  if (logw_host) {
+    e = hipMemcpy(h->lw[h->cur], logw_host, (size_t)h->N * h->tsz, hipMemcpyHostToDevice);
+    h->lw_zero = false;
+  } else {
+    e = hipMemset(h->lw[h->cur], 0, (size_t)h->N * h->tsz);
+    h->lw_zero = true;
+  }
+  if (e != hipSuccess) return hip_fail(h, e, "log-weight upload");
+  Ctl c;
+  e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "control copy");
+  c.offset = 0.0;
+  c.log_norm = log_norm;
+  c.counter = 0;
+  c.t = t;
+  for (int j = 0; j < kMaxDim; ++j) c.shift[j] = 0.0;
+  e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "control upload");
+  h->t = t;
+  return PF_OK;
+}
+
+pf_status pf_get_ancestors(pf_handle* h, uint32_t* anc_host) {
+  if (!h || !anc_host) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  if (!h->anc) return fail(h, PF_E_STATE, "created without keep_ancestors");
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  hipError_t e = hipMemcpy(anc_host, h->anc, (size_t)h->N * 4, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "ancestor copy");
+  return PF_OK;
+}
+
+pf_status pf_info(pf_handle* h, pf_info_t* out) {
+  if (!h || !out) return PF_E_INVALID;
+  std::memset(out, 0, sizeof(*out));
+  out->n_particles = h->N;
+  out->d = (uint32_t)h->d;
+  out->n_stages = (uint32_t)h->stages.size();
+  for (size_t k = 0; k < h->stages.size() && k < 32; ++k) {
+    out->radices[k] = h->stages[k].r;
+    out->tile_elems[k] = h->global ? h->g_tile : h->stages[k].r * h->stages[k].C;
+  }
+  out->global_path = h->global ? 1u : 0u;
+  out->state_dtype = (uint32_t)h->dtype;
+  out->device_bytes = h->bytes;
+  out->t = (uint32_t)h->t;
+  return PF_OK;
+}
+
+}  // extern "C"

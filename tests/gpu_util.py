@@ -1,0 +1,108 @@
+"""Helpers of the GPU parity tests: oracle-generated start states and the
+one-step comparison of the device path against the FP64 oracle.
+
+Every input of both sides comes from the oracle or the seeded generators:
+the device is given the oracle's state (rounded to the device storage
+type), never the other way round.
+"""
+from __future__ import annotations
+
+import sys
+
+import numpy as np
+
+from oracle import ButterflyOracle, State
+
+MARGIN_TOL = 1e-5          # ancestors must match where the draw's margin exceeds this
+MEAN_RTOL = 1e-4           # filter means: |dm| <= 1e-4 max(|m|, sd)
+
+
+def log(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def round_state(x: np.ndarray, logw: np.ndarray, dtype: str):
+    """Oracle state (x: (N, d) FP64) in the device's storage precision:
+    returns (device x planes (d, N), device logW, oracle x (N, d), oracle logW)
+    where the oracle arrays hold exactly the device values in FP64."""
+    from paper_1812_01502_amd import bf16_to_f32, f32_to_bf16
+    if dtype == "f64":
+        xd = np.ascontiguousarray(x.T)
+        wd = logw.copy()
+        return xd, wd, xd.T.copy(), wd.copy()
+    w32 = logw.astype(np.float32)
+    if dtype == "f32":
+        x32 = np.ascontiguousarray(x.T.astype(np.float32))
+        return x32, w32, x32.T.astype(np.float64), w32.astype(np.float64)
+    xb = f32_to_bf16(np.ascontiguousarray(x.T.astype(np.float32)))
+    return xb, w32, bf16_to_f32(xb).T.astype(np.float64), w32.astype(np.float64)
+
+
+def device_x(flt, x_raw):
+    """Device state planes (d, N) as FP64 (N, d)."""
+    from paper_1812_01502_amd import bf16_to_f32
+    if flt.dtype == "bf16":
+        x_raw = bf16_to_f32(x_raw)
+    return x_raw.astype(np.float64).T
+
+
+def tolerances(dtype: str):
+    if dtype == "f64":
+        return dict(w_atol=1e-9, x_atol=1e-9, x_rtol=1e-10, mean_rtol=1e-9, var_rtol=1e-8,
+                    ess_rtol=1e-10, ln_atol=1e-8)
+    if dtype == "f32":
+        return dict(w_atol=3e-4, x_atol=5e-5, x_rtol=2e-5, mean_rtol=MEAN_RTOL, var_rtol=2e-3,
+                    ess_rtol=2e-4, ln_atol=2e-4)
+    # BF16 storage: states carry 8 mantissa bits
+    return dict(w_atol=3e-4, x_atol=5e-5, x_rtol=8e-3, mean_rtol=MEAN_RTOL, var_rtol=2e-3,
+                ess_rtol=2e-4, ln_atol=2e-4)
+
+
+def compare_one_step(flt, orc: ButterflyOracle, x_or: np.ndarray, logw_or: np.ndarray, t: int,
+                     y, log_norm: float = 0.0, label: str = ""):
+    """Start device and oracle from the same state at step t, advance one
+    step and compare. Returns a dict of statistics (flips, errors)."""
+    dtype = flt.dtype
+    tol = tolerances(dtype)
+    xd, wd, xo, wo = round_state(x_or, logw_or, dtype)
+    flt.set_state(xd, wd, t=t, log_norm=log_norm)
+    flt.step(y)
+    rec_g = flt.estimate()
+    xg_raw, wg, tg, lng = flt.get_state()
+    anc_g = flt.ancestors().astype(np.int64)
+    st_o, rec_o = orc.step(State(x=xo, logw=wo, t=t, log_norm=log_norm), y, keep=True)
+    assert tg == t + 1
+    assert rec_g["t"] == t and rec_g["stage"] == rec_o["stage"], (rec_g["t"], rec_g["stage"], rec_o["stage"])
+    # ancestors: exact wherever the margin exceeds the tolerance
+    anc_o = rec_o["ancestors"]
+    mism = anc_g != anc_o
+    bad = mism & (rec_o["margin"] > MARGIN_TOL)
+    assert not np.any(bad), (label, "ancestor mismatch beyond margin", np.nonzero(bad)[0][:8],
+                             anc_g[bad][:8], anc_o[bad][:8], rec_o["margin"][bad][:8])
+    # every device ancestor lies in its group
+    N = flt.n
+    r, R = rec_o["radix"], rec_o["stride"]
+    i = np.arange(N)
+    assert np.array_equal((anc_g // (r * R), anc_g % R), (i // (r * R), i % R)) or r == N
+    # new log-weights (normalised so that the max is 0)
+    dw = np.abs(wg.astype(np.float64) - st_o.logw)
+    assert np.max(dw) <= tol["w_atol"], (label, "logw", float(np.max(dw)))
+    # propagated states where the ancestor agrees
+    xg = device_x(flt, xg_raw)
+    ok = ~mism
+    err = np.abs(xg[ok] - st_o.x[ok])
+    lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st_o.x[ok])
+    assert np.all(err <= lim), (label, "x", float(np.max(err - lim)))
+    # estimates of the step (R13 for the means)
+    sd = np.sqrt(rec_o["var"])
+    dm = np.abs(rec_g["mean"] - rec_o["mean"])
+    assert np.all(dm <= tol["mean_rtol"] * np.maximum(np.abs(rec_o["mean"]), sd)), (label, "mean", dm, sd)
+    dv = np.abs(rec_g["var"] - rec_o["var"])
+    assert np.all(dv <= tol["var_rtol"] * rec_o["var"] + 1e-12), (label, "var", dv, rec_o["var"])
+    assert abs(rec_g["ess"] - rec_o["ess"]) <= tol["ess_rtol"] * rec_o["ess"], (label, "ess")
+    assert abs(lng - rec_o["log_norm"]) <= tol["ln_atol"] * (1 + abs(rec_o["log_norm"] - log_norm)), \
+        (label, "log_norm", lng, rec_o["log_norm"])
+    return dict(flips=int(mism.sum()), near=int(np.sum(rec_o["margin"] <= MARGIN_TOL)),
+                max_dw=float(np.max(dw)), max_dx=float(np.max(err)) if err.size else 0.0,
+                max_dm=float(np.max(dm / np.maximum(np.abs(rec_o["mean"]), sd))))

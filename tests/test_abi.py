@@ -1,0 +1,164 @@
+"""CPU checks of the C-ABI library: it loads, exports every function that
+include/pf.h declares, its ctypes layouts match the C header, and host-side
+argument validation reports errors without touching a GPU."""
+import ctypes
+import os
+import re
+import shutil
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pf.h")
+
+
+def _declared_functions():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"^\s*(?:const\s+)?\w+\s*\*?\s*(pf_\w+)\s*\(", src, flags=re.M)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1812_01502_amd import _lib
+    if not os.path.exists(_lib.LIB_PATH):
+        pytest.fail("libpf.so is not built (run __graft_entry__.build())")
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1812_01502_amd import _lib
+    declared = _declared_functions()
+    assert len(declared) >= 14
+    assert sorted(_lib.EXPORTS) == declared
+    out = subprocess.run(["nm", "-D", "--defined-only", _lib.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = set(re.findall(r" T (pf_\w+)$", out, flags=re.M))
+    for name in declared:
+        assert name in exported, name
+        assert hasattr(lib, name)
+
+
+def test_struct_layouts_match_header():
+    """sizeof/offsetof of the public structs from a C compiler equal ctypes'."""
+    from paper_1812_01502_amd import _lib as L
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    fields = {
+        "pf_model": ("PfModel", ["kind", "d", "A", "Q_chol", "H", "R_chol", "m0", "P0_chol",
+                                 "phi", "sigma", "beta"]),
+        "pf_config": ("PfConfig", ["n_particles", "radix", "resampler", "state_dtype", "seed",
+                                   "stream_id", "history", "keep_ancestors", "reserved"]),
+        "pf_estimate_t": ("PfEstimate", ["t", "stage", "radix", "valid", "log_normaliser", "ess",
+                                         "max_log_weight", "next_offset", "mean", "var"]),
+        "pf_info_t": ("PfInfo", ["n_particles", "d", "n_stages", "radices", "global_path",
+                                 "state_dtype", "device_bytes", "t", "tile_elems"]),
+    }
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(){"]
+    for cname, (_, fl) in fields.items():
+        lines.append(f'printf("{cname} %zu\\n", sizeof({cname}));')
+        for f in fl:
+            lines.append(f'printf("{cname}.{f} %zu\\n", offsetof({cname}, {f}));')
+    lines.append("return 0;}")
+    d = tempfile.mkdtemp()
+    try:
+        src = os.path.join(d, "l.c")
+        open(src, "w").write("\n".join(lines))
+        exe = os.path.join(d, "l")
+        subprocess.run([cc, src, "-o", exe], check=True)
+        out = subprocess.run([exe], capture_output=True, text=True, check=True).stdout
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    got = dict(line.split() for line in out.strip().splitlines())
+    for cname, (pyname, fl) in fields.items():
+        cls = getattr(L, pyname)
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for f in fl:
+            assert int(got[f"{cname}.{f}"]) == getattr(cls, f).offset, (cname, f)
+
+
+def _model_lg(d=2):
+    from paper_1812_01502_amd import _lib as L
+    keep = [np.eye(d) for _ in range(5)] + [np.zeros(d)]
+    m = L.PfModel()
+    m.kind, m.d = L.PF_MODEL_LG, d
+    for nm, a in zip(("A", "Q_chol", "H", "R_chol", "P0_chol", "m0"), keep):
+        setattr(m, nm, a.ctypes.data_as(L.DPTR))
+    return m, keep
+
+
+def _cfg(n=1024, radix=2, resampler=0, dtype=0):
+    from paper_1812_01502_amd import _lib as L
+    c = L.PfConfig()
+    c.n_particles, c.radix, c.resampler, c.state_dtype, c.seed = n, radix, resampler, dtype, 1
+    return c
+
+
+@pytest.mark.parametrize("case", ["n_not_pow2", "n_one", "radix_3", "radix_1", "dtype_bad",
+                                  "resampler_bad", "d_zero", "d_17", "null_matrix",
+                                  "not_lower", "neg_diag", "nan_entry", "sv_phi"])
+def test_create_rejects_invalid_arguments(lib, case):
+    from paper_1812_01502_amd import _lib as L
+    m, keep = _model_lg(2)
+    c = _cfg()
+    if case == "n_not_pow2":
+        c.n_particles = 1000
+    elif case == "n_one":
+        c.n_particles = 1
+    elif case == "radix_3":
+        c.radix = 3
+    elif case == "radix_1":
+        c.radix = 1
+    elif case == "dtype_bad":
+        c.state_dtype = 7
+    elif case == "resampler_bad":
+        c.resampler = 5
+    elif case == "d_zero":
+        m.d = 0
+    elif case == "d_17":
+        m.d = 17
+    elif case == "null_matrix":
+        m.A = ctypes.cast(None, L.DPTR)
+    elif case == "not_lower":
+        bad = np.array([[1.0, 0.5], [0.0, 1.0]])
+        keep.append(bad)
+        m.Q_chol = bad.ctypes.data_as(L.DPTR)
+    elif case == "neg_diag":
+        bad = np.array([[-1.0, 0.0], [0.0, 1.0]])
+        keep.append(bad)
+        m.R_chol = bad.ctypes.data_as(L.DPTR)
+    elif case == "nan_entry":
+        bad = np.array([[np.nan, 0.0], [0.0, 1.0]])
+        keep.append(bad)
+        m.A = bad.ctypes.data_as(L.DPTR)
+    elif case == "sv_phi":
+        m = L.PfModel()
+        m.kind, m.d, m.phi, m.sigma, m.beta = L.PF_MODEL_SV, 1, 1.0, 0.25, 0.6
+    h = ctypes.c_void_p()
+    st = lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h))
+    assert st == -1, (case, st, lib.pf_last_error(None))
+    assert h.value is None
+    assert lib.pf_last_error(None)
+
+
+def test_unsupported_radix_reported(lib):
+    """A stage radix the tile kernels cannot hold is refused before any
+    device work (r = 8192 with N = 2^20: two stages of 8192, then 16)."""
+    m, keep = _model_lg(2)
+    c = _cfg(n=1 << 20, radix=8192)
+    h = ctypes.c_void_p()
+    st = lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h))
+    assert st == -2
+    assert b"radix" in lib.pf_last_error(None)
+
+
+def test_misc_entry_points_without_device(lib):
+    assert lib.pf_destroy(None) == 0
+    assert lib.pf_status_string(0) == b"ok"
+    assert lib.pf_status_string(-5) == b"non-finite value"
+    assert lib.pf_step(None, None) == -1
+    assert lib.pf_sync(None) == -1
