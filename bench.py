@@ -125,6 +125,8 @@ def main():
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--extra-radices", default="2,4,32")
+    ap.add_argument("--workload", choices=["lg8", "sv"], default="lg8",
+                    help="lg8: 8-D LG, N = 2^20 (default); sv: stochastic volatility, N = 2^24")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -138,7 +140,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.load_library()
-    cfg = W.config("c2")
+    cfg = W.config("c2" if args.workload == "lg8" else "c3")
+    if args.workload == "sv" and args.n == 1 << 20:
+        args.n = cfg["N"]
     model, N, d = cfg["model"], args.n, cfg["model"].d
     K, Wm = args.steps, args.warmup
     _, ys = W.simulate(model, Wm + K, seed=cfg["seed_obs"])
@@ -215,7 +219,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"lg8 N=2^{N.bit_length() - 1} radix {args.radix}",
+        "config": {"workload": f"{args.workload} N=2^{N.bit_length() - 1} radix {args.radix}",
                    "n_particles": N, "state_dim": d, "radix": args.radix, "stages": plan,
                    "resampler": "multinomial", "steps_per_run": K, "observations": "device"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",

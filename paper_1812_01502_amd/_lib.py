@@ -7,7 +7,8 @@ import os
 from ctypes import POINTER, c_char_p, c_double, c_int32, c_uint32, c_uint64, c_void_p
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libpf.so")
+# PF_LIBRARY may name another build of the same library (e.g. a tuning build)
+LIB_PATH = os.environ.get("PF_LIBRARY") or os.path.join(HERE, "libpf.so")
 
 PF_MAX_DIM = 16
 

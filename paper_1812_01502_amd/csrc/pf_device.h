@@ -154,17 +154,22 @@ __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, double& zc,
   zs = rho * s;
 }
 
-// Resampling uniforms (u0, u1) of pair p and the normals z[e][j] of its two
-// particles for dimensions j < d (entries j >= d are left untouched), from
-// counter (p, tau, block, stream).
-template <int D, typename T>
-__device__ __forceinline__ void pair_randoms(uint32_t p, uint32_t tau, uint32_t sid, uint32_t k0,
-                                             uint32_t k1, int d, T& u0, T& u1, T (&z0)[D],
-                                             T (&z1)[D]) {
+// Block 0 of pair p: the resampling uniforms (u0, u1) of the pair's two
+// particles and their dimension-0 normals (z0, z1).
+template <typename T>
+__device__ __forceinline__ void pair_block0(uint32_t p, uint32_t tau, uint32_t sid, uint32_t k0,
+                                            uint32_t k1, T& u0, T& u1, T& z0, T& z1) {
   const Words b0 = philox(p, tau, 0u, sid, k0, k1);
   u0 = word_uniform<T>(b0.w0);
   u1 = word_uniform<T>(b0.w1);
-  box_muller(b0.w2, b0.w3, z0[0], z1[0]);
+  box_muller(b0.w2, b0.w3, z0, z1);
+}
+
+// Blocks b >= 1 of pair p: normals of dimensions 2b-1 and 2b (< d) of both
+// particles; entries j >= d and j = 0 are left untouched.
+template <int D, typename T>
+__device__ __forceinline__ void pair_normals_rest(uint32_t p, uint32_t tau, uint32_t sid, uint32_t k0,
+                                                  uint32_t k1, int d, T (&z0)[D], T (&z1)[D]) {
 #pragma unroll
   for (int b = 1; 2 * b - 1 < D; ++b) {
     if (2 * b - 1 < d) {
@@ -173,6 +178,15 @@ __device__ __forceinline__ void pair_randoms(uint32_t p, uint32_t tau, uint32_t 
       if (2 * b < D && 2 * b < d) box_muller(w.w2, w.w3, z0[2 * b], z1[2 * b]);
     }
   }
+}
+
+// Uniforms and all normals of pair p (counter (p, tau, block, stream)).
+template <int D, typename T>
+__device__ __forceinline__ void pair_randoms(uint32_t p, uint32_t tau, uint32_t sid, uint32_t k0,
+                                             uint32_t k1, int d, T& u0, T& u1, T (&z0)[D],
+                                             T (&z1)[D]) {
+  pair_block0<T>(p, tau, sid, k0, k1, u0, u1, z0[0], z1[0]);
+  pair_normals_rest<D, T>(p, tau, sid, k0, k1, d, z0, z1);
 }
 
 // Normals only (prior draws at tau = 0).
@@ -293,32 +307,77 @@ template <int D, typename T> struct Model<D, MK_SV, T> {
 // ---------------------------------------------------------------------------
 // Per-handle control block in device memory.
 // ---------------------------------------------------------------------------
+// The maximum of the new log-weights of a step (the offset subtracted at the
+// next load) is gathered in kOffSlots slots, one cache line apart, so that
+// the tiles' atomicMax operations spread over memory channels; a ring of 3
+// steps lets the offset of step t be read while step t+1's is gathered and
+// step t+2's slots are cleared.
+constexpr int kOffSlots = 32;
+constexpr int kOffStride = 16;   // 16 x 8 B = one 128-B line per slot
+constexpr int kOffRing = 3;
+constexpr int kOffEntries = kOffRing * kOffSlots * kOffStride;
+
 struct Ctl {
   double log_norm;           // running log-normaliser (FP64)
-  double offset;             // max of the stored log-weights (subtracted at load)
-  double shift[kMaxDim];     // reference point of the variance sums (last mean)
-  uint32_t counter;          // last-block-done ticket
-  uint32_t t;                // completed steps (diagnostic)
-  uint32_t pad[2];
+  uint32_t t;                // steps reduced so far (diagnostic)
+  uint32_t pad[13];
+  long long offs[kOffEntries];  // encoded maxima, [ring][slot * stride]
 };
 
-// Per-tile partial record: [m, S, sw2, swin, lwmax, A1[D], A2[D]] where
-// m is the tile max of l, S = sum e^{l-m}, sw2 = sum e^{2(l-m)},
-// swin = sum e^{logW}, lwmax = max of the new log-weights, A1 = sum
-// e^{l-m}(x - shift), A2 = sum e^{l-m}(x - shift)^2.
-__host__ __device__ constexpr int partial_stride(int D) { return 5 + 2 * D; }
+// Per-tile partial record: [m, S, sw2, swin, A1[D], A2[D], sh[D]].
+__host__ __device__ constexpr int partial_stride(int D) { return 4 + 3 * D; }
 
 // ---------------------------------------------------------------------------
-// Wave-level helpers (wave64).
+// Wave-level helpers (wave64). FP32 reductions use DPP lane moves (VALU)
+// instead of LDS-routed shuffles: xor-1, xor-2 quad permutes, half-row and
+// row mirrors (16-lane rows), then row broadcasts 15 and 31; the total ends
+// in lane 63 and is broadcast with readlane.
 // ---------------------------------------------------------------------------
-template <typename T> __device__ __forceinline__ T wave_sum(T v) {
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ float dpp_f(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v), CTRL,
+                                                                ROW_MASK, 0xF, false));
+}
+constexpr int kDppQuadXor1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowBcast15 = 0x142;
+constexpr int kDppRowBcast31 = 0x143;
+
+__device__ __forceinline__ float wave_sum(float v) {
+  v += dpp_f<kDppQuadXor1>(v);
+  v += dpp_f<kDppQuadXor2>(v);
+  v += dpp_f<kDppRowHalfMirror>(v);
+  v += dpp_f<kDppRowMirror>(v);
+  v += dpp_f<kDppRowBcast15, 0xA>(v);
+  v += dpp_f<kDppRowBcast31, 0xC>(v);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ float wave_max(float v) {
+  // disabled rows of the broadcasts receive 0 from update_dpp: use the
+  // identity -inf explicitly there
+  v = fmaxf(v, dpp_f<kDppQuadXor1>(v));
+  v = fmaxf(v, dpp_f<kDppQuadXor2>(v));
+  v = fmaxf(v, dpp_f<kDppRowHalfMirror>(v));
+  v = fmaxf(v, dpp_f<kDppRowMirror>(v));
+  const int lane = __lane_id();
+  float b15 = dpp_f<kDppRowBcast15, 0xA>(v);
+  if (((lane >> 4) & 1) == 0) b15 = v;
+  v = fmaxf(v, b15);
+  float b31 = dpp_f<kDppRowBcast31, 0xC>(v);
+  if ((lane >> 5) == 0) b31 = v;
+  v = fmaxf(v, b31);
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
+}
+__device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
   for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
   return v;
 }
-template <typename T> __device__ __forceinline__ T wave_max(T v) {
+__device__ __forceinline__ double wave_max(double v) {
 #pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v = fmaxT(v, __shfl_xor(v, s, 64));
+  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
   return v;
 }
 // Inclusive prefix sum over the 64 lanes.

@@ -3,18 +3,21 @@
 // Butterfly path (radix r < N), one fused kernel per step:
 //   phase A  coalesced load of a tile of r x C particles (C contiguous
 //            columns per group row, rows at the stage stride R), log-weight
-//            l = logW - offset + log g(x, y_t), Philox randoms, per-tile
-//            estimate partials; states and scalars staged in LDS
+//            l = logW - offset + log g(x, y_t), the pair's block-0 randoms,
+//            per-tile estimate partials; states and scalars staged in LDS
 //   phase B  per group (a column of the tile): max, exp, inclusive scan,
 //            carried weight m_G + ln c_{r-1} - ln r, inverse-CDF draw.
-//            r <= 64: one wave segment per group (cross-lane shuffles);
+//            r <= 64: one wave segment per group (DPP row operations and
+//            cross-lane permutes, two groups per wave at a time);
 //            r > 64: 64-member chunks with LDS chunk prefixes.
-//   phase C  gather of the ancestor from LDS, propagation with the
-//            step's normals, coalesced store of x and the new log-weight
-//   tail     the last tile to finish reduces all tile partials in FP64 in a
-//            fixed order (estimate record, log-normaliser, next offset).
-// Global path (r >= N): weight + tile scan, grid prefix (+ finalize),
-// draw + gather + propagate.
+//   phase C  remaining normals, gather of the ancestor from LDS,
+//            propagation, coalesced store of x and the new log-weight.
+// Block 0 of every step kernel is not a tile: it reduces the previous
+// step's tile partials (estimate record, log-normaliser) while the tiles
+// run. The offset subtracted from the stored log-weights at the next load
+// (their maximum) is gathered with an order-preserving integer atomicMax.
+// Global path (r >= N): weight + tile scan, grid prefix, draw + gather +
+// propagate.
 #pragma once
 
 #include "pf_device.h"
@@ -30,7 +33,9 @@ template <typename T, typename S> struct StepArgs {
   const T* y_dev;           // nullable: observation (d values) in device memory
   T y_val[kMaxDim];         // observation passed by value when y_dev == nullptr
   const ModelParams<T>* mp;
-  T* partials;
+  T* part_out;              // tile partials of this step
+  const T* part_prev;       // nullable: partials of the previous step, still to reduce
+  uint32_t ntiles_prev, t_prev, k_prev, radix_prev;
   Ctl* ctl;
   pf_estimate_t* hist;
   uint32_t hist_cap;
@@ -50,6 +55,43 @@ template <typename T, typename S> struct StepArgs {
   double* gpre;              // tile prefix, ntiles + 1 entries
   double* gscale;            // e^{m_b - M}, ntiles entries
 };
+
+// ---------------------------------------------------------------------------
+// Order-preserving encoding of a double as a signed 64-bit integer (for a
+// deterministic atomicMax of the new log-weights).
+// ---------------------------------------------------------------------------
+__host__ __device__ inline long long ord_encode(double v) {
+  long long b;
+  __builtin_memcpy(&b, &v, 8);
+  return b >= 0 ? b : (b ^ 0x7FFFFFFFFFFFFFFFLL);
+}
+__host__ __device__ inline double ord_decode(long long e) {
+  const long long b = e >= 0 ? e : (e ^ 0x7FFFFFFFFFFFFFFFLL);
+  double v;
+  __builtin_memcpy(&v, &b, 8);
+  return v;
+}
+
+__device__ __forceinline__ long long* off_slot(Ctl* c, uint32_t step, uint32_t slot) {
+  return c->offs + (size_t)(step % kOffRing) * kOffSlots * kOffStride + (size_t)slot * kOffStride;
+}
+// Max over the slots of `step` (every lane of the calling wave gets it).
+__device__ __forceinline__ double read_offset(const Ctl* c, uint32_t step) {
+  const uint32_t lane = threadIdx.x & 63u;
+  const long long* base = c->offs + (size_t)(step % kOffRing) * kOffSlots * kOffStride;
+  long long v = lane < (uint32_t)kOffSlots ? base[(size_t)lane * kOffStride] : LLONG_MIN;
+#pragma unroll
+  for (int s = 32; s >= 1; s >>= 1) {
+    const long long o = __shfl_xor(v, s, 64);
+    v = o > v ? o : v;
+  }
+  return ord_decode(v);
+}
+// Reset the slots of `step` (by threads 0..kOffSlots-1 of a block).
+__device__ __forceinline__ void clear_offset(Ctl* c, uint32_t step, double first) {
+  if (threadIdx.x < (uint32_t)kOffSlots)
+    *off_slot(c, step, threadIdx.x) = ord_encode(threadIdx.x == 0 ? first : -INFINITY);
+}
 
 // ---------------------------------------------------------------------------
 // Initialisation (Algorithm 1): x_0 = prior(z(tau = 0)), logW = 0, control
@@ -73,12 +115,14 @@ __global__ void __launch_bounds__(256) pf_init_kernel(StepArgs<T, S> a) {
     a.lw_out[2 * p] = 0;
     a.lw_out[2 * p + 1] = 0;
   }
-  if (blockIdx.x == 0 && threadIdx.x == 0) {
-    a.ctl->log_norm = 0.0;
-    a.ctl->offset = 0.0;
-    for (int j = 0; j < kMaxDim; ++j) a.ctl->shift[j] = 0.0;
-    a.ctl->counter = 0u;
-    a.ctl->t = 0u;
+  if (blockIdx.x == 0) {
+    clear_offset(a.ctl, 0u, 0.0);
+    clear_offset(a.ctl, 1u, -INFINITY);
+    clear_offset(a.ctl, 2u, -INFINITY);
+    if (threadIdx.x == 0) {
+      a.ctl->log_norm = 0.0;
+      a.ctl->t = 0u;
+    }
   }
 }
 
@@ -98,18 +142,13 @@ __device__ __forceinline__ T block_max(T v, T* red /* NT/64 */) {
   return m;
 }
 
-// Arguments of the final reduction.
+// What the reduction of one step's partials needs.
 struct FinArgs {
   Ctl* ctl;
   pf_estimate_t* hist;
   uint32_t hist_cap, t, k, radix, d;
   uint64_t N;
 };
-
-template <typename T> __device__ __forceinline__ double ld_partial(const T* p, bool coherent) {
-  return coherent ? (double)__hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)
-                  : (double)*p;
-}
 
 __device__ __forceinline__ double wave_sum_d(double v) {
 #pragma unroll
@@ -122,64 +161,65 @@ __device__ __forceinline__ double wave_max_d(double v) {
   return v;
 }
 
-// Final FP64 reduction of the tile partials by one block, in a fixed order
+// FP64 reduction of one step's tile partials by one block, in a fixed order
 // (thread i takes tiles i, i + NT, ...; waves reduce by a fixed butterfly;
-// wave results are added in wave order). Writes the estimate record of step
-// t and advances the control block. `red` needs (NT/64) * (5 + 2D) doubles.
+// wave results are added in wave order). Partial record of tile b:
+// [m, S, sw2, swin, A1[D], A2[D], sh[D]] with m the tile max of l,
+// w = e^{l - m}, S = sum w, sw2 = sum w^2, swin = sum e^{logW},
+// A1 = sum w (x - sh), A2 = sum w (x - sh)^2, sh a tile reference point.
+// Writes the estimate record of step f.t and adds its log-normaliser
+// increment. `red` needs (NT/64) * (4 + 2D) doubles.
 template <int D, typename T, int NT>
 __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, uint32_t ntiles,
-                                  double* red, bool coherent, bool reset_counter) {
+                                  double* red) {
   constexpr int PS = partial_stride(D);
+  constexpr int NV = 4 + 2 * D;  // accumulated values: m(unused), S, sw2, swin, Mx[D], Mxx[D]
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  double m = -INFINITY, lwmax = -INFINITY;
-  for (uint32_t b = tid; b < ntiles; b += NT) {
-    m = fmax(m, ld_partial(part + (size_t)b * PS, coherent));
-    lwmax = fmax(lwmax, ld_partial(part + (size_t)b * PS + 4, coherent));
-  }
+  const int d = (int)f.d;
+  double m = -INFINITY;
+  for (uint32_t b = tid; b < ntiles; b += NT) m = fmax(m, (double)part[(size_t)b * PS]);
   m = wave_max_d(m);
-  lwmax = wave_max_d(lwmax);
-  if (lane == 0) {
-    red[wv * 2] = m;
-    red[wv * 2 + 1] = lwmax;
-  }
+  if (lane == 0) red[wv] = m;
   __syncthreads();
-  double M = red[0], LWM = red[1];
-  for (int w = 1; w < NW; ++w) {
-    M = fmax(M, red[w * 2]);
-    LWM = fmax(LWM, red[w * 2 + 1]);
-  }
+  double M = red[0];
+  for (int w = 1; w < NW; ++w) M = fmax(M, red[w]);
   __syncthreads();
-  double acc[PS];
+  double acc[NV];
 #pragma unroll
-  for (int v = 0; v < PS; ++v) acc[v] = 0.0;
+  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
   for (uint32_t b = tid; b < ntiles; b += NT) {
     const T* pr = part + (size_t)b * PS;
-    const double e = exp(ld_partial(pr, coherent) - M);
-    acc[1] += e * ld_partial(pr + 1, coherent);
-    acc[2] += e * e * ld_partial(pr + 2, coherent);
-    acc[3] += ld_partial(pr + 3, coherent);
+    const double e = exp((double)pr[0] - M);
+    const double Sb = (double)pr[1];
+    acc[1] += e * Sb;
+    acc[2] += e * e * (double)pr[2];
+    acc[3] += (double)pr[3];
 #pragma unroll
-    for (int v = 5; v < PS; ++v) acc[v] += e * ld_partial(pr + v, coherent);
+    for (int j = 0; j < D; ++j) {
+      if (j < d) {
+        const double a1 = (double)pr[4 + j], a2 = (double)pr[4 + D + j], s = (double)pr[4 + 2 * D + j];
+        acc[4 + j] += e * (a1 + Sb * s);
+        acc[4 + D + j] += e * (a2 + 2.0 * s * a1 + Sb * s * s);
+      }
+    }
   }
 #pragma unroll
-  for (int v = 1; v < PS; ++v) {
-    if (v == 4) continue;
-    if (v >= 5 + (int)f.d && v < 5 + D) continue;
-    if (v >= 5 + D + (int)f.d) continue;
+  for (int v = 1; v < NV; ++v) {
+    if ((v >= 4 + d && v < 4 + D) || v >= 4 + D + d) continue;
     acc[v] = wave_sum_d(acc[v]);
   }
   if (lane == 0) {
 #pragma unroll
-    for (int v = 0; v < PS; ++v) red[wv * PS + v] = acc[v];
+    for (int v = 0; v < NV; ++v) red[wv * NV + v] = acc[v];
   }
   __syncthreads();
   if (tid == 0) {
-    double tot[PS];
+    double tot[NV];
 #pragma unroll
-    for (int v = 0; v < PS; ++v) {
+    for (int v = 0; v < NV; ++v) {
       tot[v] = red[v];
-      for (int w = 1; w < NW; ++w) tot[v] += red[w * PS + v];
+      for (int w = 1; w < NW; ++w) tot[v] += red[w * NV + v];
     }
     const double S = tot[1], sw2 = tot[2], swin = tot[3];
     pf_estimate_t* rec = f.hist + (f.t % f.hist_cap);
@@ -192,47 +232,59 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
     rec->log_normaliser = ln;
     rec->ess = S * S / ((double)f.N * sw2);
     rec->max_log_weight = M;
-    rec->next_offset = LWM;
+    double nx = -INFINITY;
+    for (int sl = 0; sl < kOffSlots; ++sl) nx = fmax(nx, ord_decode(*off_slot(f.ctl, f.t + 1, sl)));
+    rec->next_offset = nx;
 #pragma unroll
     for (int j = 0; j < kMaxDim; ++j) {
       double mean = 0.0, var = 0.0;
-      if (j < D && j < (int)f.d) {
-        const double m1 = tot[5 + (j < D ? j : 0)] / S;
-        const double m2 = tot[5 + D + (j < D ? j : 0)] / S;
-        mean = f.ctl->shift[j] + m1;
-        var = fmax(m2 - m1 * m1, 0.0);
-        f.ctl->shift[j] = mean;
+      if (j < D && j < d) {
+        const int jj = j < D ? j : 0;
+        mean = tot[4 + jj] / S;
+        var = fmax(tot[4 + D + jj] / S - mean * mean, 0.0);
       }
       rec->mean[j] = mean;
       rec->var[j] = var;
     }
     f.ctl->log_norm = ln;
-    f.ctl->offset = LWM;
     f.ctl->t = f.t + 1;
-    if (reset_counter)
-      __hip_atomic_store(&f.ctl->counter, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 }
 
-template <typename T, typename S> __device__ __forceinline__ FinArgs fin_args(const StepArgs<T, S>& a) {
+// Stand-alone reduction of the last step's partials (one block).
+template <int D, typename T, int NT>
+__global__ void __launch_bounds__(NT) pf_finalize_kernel(FinArgs f, const T* part, uint32_t ntiles) {
+  __shared__ double red[(NT / 64) * (4 + 2 * D)];
+  finalize_partials<D, T, NT>(f, part, ntiles, red);
+}
+
+template <typename T, typename S> __device__ __forceinline__ FinArgs prev_fin_args(const StepArgs<T, S>& a) {
   FinArgs f;
   f.ctl = a.ctl;
   f.hist = a.hist;
   f.hist_cap = a.hist_cap;
-  f.t = a.t;
-  f.k = a.k;
-  f.radix = a.radix;
+  f.t = a.t_prev;
+  f.k = a.k_prev;
+  f.radix = a.radix_prev;
   f.d = a.d;
   f.N = a.N;
   return f;
 }
 
-// Partial sums of one tile from per-thread register values. Every thread
-// holds nloc (l, x, logW) triples; returns after thread PS-1 of the block
-// has written the record. `red` needs (NT/64) * (5 + 2D) values of T.
+// Block 0 of a step kernel: reduce the previous step's partials, and clear
+// the offset slot that the next step will accumulate into.
+template <int D, typename T, typename S, int NT>
+__device__ void step_head_block(const StepArgs<T, S>& a, double* red) {
+  clear_offset(a.ctl, a.t + 2, -INFINITY);
+  if (a.part_prev) finalize_partials<D, T, NT>(prev_fin_args(a), a.part_prev, a.ntiles_prev, red);
+}
+
+// Partial sums of one tile from per-thread register values (relative to the
+// tile max `mtile` and the tile reference point `sh`). Thread v < PS of the
+// block writes slot v. `red` needs (NT/64) * PS values of T.
 template <int D, typename T, int NT, int NLOC>
 __device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[NLOC][D],
-                                              const T (&lwn)[NLOC], const T (&shift)[D], int d,
+                                              const T (&lwn)[NLOC], const T (&sh)[D], int d,
                                               T mtile, T* red, T* out /* PS values */) {
   constexpr int PS = partial_stride(D);
   T s = 0, sw2 = 0, swin = 0, a1[D], a2[D];
@@ -246,7 +298,7 @@ __device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[N
     swin += fexp(lwn[e]);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      const T dx = x[e][j] - shift[j];
+      const T dx = x[e][j] - sh[j];
       const T wd = w * dx;
       a1[j] += wd;
       a2[j] += wd * dx;
@@ -270,21 +322,23 @@ __device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[N
     rw[3] = swin;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      rw[5 + j] = a1[j];
-      rw[5 + D + j] = a2[j];
+      rw[4 + j] = a1[j];
+      rw[4 + D + j] = a2[j];
     }
   }
   __syncthreads();
   if (threadIdx.x < PS) {
     const int v = threadIdx.x;
     T acc = 0;
-    if (v == 0) acc = mtile;
-    else if (v != 4) {
+    if (v == 0) {
+      acc = mtile;
+    } else if (v < 4 + 2 * D) {
 #pragma unroll
       for (int w = 0; w < NT / 64; ++w) acc += red[w * PS + v];
+    } else {
+      acc = sh[v - 4 - 2 * D < D ? v - 4 - 2 * D : 0];
     }
-    // device-coherent store: read by whichever tile finishes last
-    if (v != 4) __hip_atomic_store(&out[v], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    out[v] = acc;
   }
 }
 
@@ -333,12 +387,12 @@ __device__ __forceinline__ void tile_coords(const TileGeo& g, uint32_t f, uint32
   }
 }
 
-// Block index -> tile: each of the 8 XCDs (blocks are dealt round-robin)
-// gets a contiguous range of tiles, so neighbouring column chunks share
-// the XCD's L2.
-__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t nb) {
-  if ((nb & 7u) != 0u) return b;
-  return (b & 7u) * (nb >> 3) + (b >> 3);
+// Tile index of block b (1..nb; block 0 is the head block). Blocks are dealt
+// round-robin to the 8 XCDs; each XCD gets a contiguous range of tiles, so
+// neighbouring column chunks share the XCD's L2.
+__device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
+  if ((ntiles & 7u) != 0u) return b;
+  return (b & 7u) * (ntiles >> 3) + (b >> 3);
 }
 
 // Bump allocator over the dynamic LDS block: offsets are plain integers so
@@ -357,30 +411,96 @@ __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint3
                                                  uint32_t pad, int NT, bool blockpath) {
   const size_t E = (size_t)r * C;
   const size_t P = r + pad;
+  const size_t PS = 4 + 3 * (size_t)D;
   size_t b = 0;
   auto add = [&](size_t n) { b = (b + n + 15) & ~(size_t)15; };
-  add((size_t)d * E * tsz);      // xs
-  add(C * P * tsz);              // l / cdf
-  add(C * P * tsz);              // uniforms
-  add(C * P * 4);                // ancestor positions
-  add(C * tsz);                  // carried weight per column
-  add((size_t)(NT / 64) * (5 + 2 * D) * tsz);  // reduction scratch
+  add((size_t)d * E * tsz);                       // xs
+  add(C * P * tsz);                               // l / cdf
+  add(C * P * tsz);                               // uniforms, then ancestor positions
+  const size_t red = (size_t)(NT / 64) * PS * tsz;
+  add(red > C * tsz ? red : C * tsz);             // reduction scratch / carried weight
+  add((size_t)(D > NT / 64 ? D : NT / 64) * tsz);  // tile reference point / wave maxima
   if (blockpath) {
     add((E / 64) * tsz);  // chunk max
     add((E / 64) * tsz);  // chunk sums
     add(C * tsz);         // column max
     add(C * tsz);         // column total
+    add(C * tsz);         // first member's uniform
   }
-  size_t fin = (size_t)(NT / 64) * (5 + 2 * D) * 8;  // finalize scratch (doubles), reuses the front
+  const size_t fin = (size_t)(NT / 64) * (4 + 2 * D) * 8;  // head block: finalize scratch
   return b > fin ? b : fin;
 }
 
 // ---------------------------------------------------------------------------
-// Fused butterfly step (radix r < N). One block per tile of r x C particles.
+// Segmented wave operations for groups of r = 2^lr <= 64 lanes (FP32: DPP
+// row operations; FP64: cross-lane shuffles).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ float seg_max(float v, uint32_t lr, uint32_t lane) {
+  v = fmaxf(v, dpp_f<kDppQuadXor1>(v));
+  if (lr >= 2) v = fmaxf(v, dpp_f<kDppQuadXor2>(v));
+  if (lr >= 3) v = fmaxf(v, dpp_f<kDppRowHalfMirror>(v));
+  if (lr >= 4) v = fmaxf(v, dpp_f<kDppRowMirror>(v));
+  if (lr >= 5) {
+    float b = dpp_f<kDppRowBcast15, 0xA>(v);
+    if (((lane >> 4) & 1u) == 0u) b = v;
+    v = fmaxf(v, b);
+    if (lr >= 6) {
+      float c = dpp_f<kDppRowBcast31, 0xC>(v);
+      if ((lane >> 5) == 0u) c = v;
+      v = fmaxf(v, c);
+    }
+    v = __shfl(v, (int)(lane | ((1u << lr) - 1u)), 64);  // the segment's last lane
+  }
+  return v;
+}
+__device__ __forceinline__ float seg_scan(float v, uint32_t lr, uint32_t q) {
+  float o = dpp_f<0x111>(v);  // row_shr:1
+  if (q >= 1u) v += o;
+  if (lr >= 2) {
+    o = dpp_f<0x112>(v);      // row_shr:2
+    if (q >= 2u) v += o;
+  }
+  if (lr >= 3) {
+    o = dpp_f<0x114>(v);      // row_shr:4
+    if (q >= 4u) v += o;
+  }
+  if (lr >= 4) {
+    o = dpp_f<0x118>(v);      // row_shr:8
+    if (q >= 8u) v += o;
+  }
+  if (lr >= 5) {
+    o = dpp_f<kDppRowBcast15, 0xA>(v);
+    if ((q >> 4) & 1u) v += o;
+  }
+  if (lr >= 6) {
+    o = dpp_f<kDppRowBcast31, 0xC>(v);
+    if (q >= 32u) v += o;
+  }
+  return v;
+}
+__device__ __forceinline__ double seg_max(double v, uint32_t lr, uint32_t lane) {
+  for (uint32_t s = 1; s < (1u << lr); s <<= 1) v = fmax(v, __shfl_xor(v, (int)s, 64));
+  return v;
+}
+__device__ __forceinline__ double seg_scan(double v, uint32_t lr, uint32_t q) {
+  for (uint32_t s = 1; s < (1u << lr); s <<= 1) {
+    const double o = __shfl_up(v, s, 64);
+    if (q >= s) v += o;
+  }
+  return v;
+}
+
+// ---------------------------------------------------------------------------
+// Fused butterfly step (radix r < N). Block 0 is the head block; block
+// b >= 1 processes a tile of r x C particles.
 // ---------------------------------------------------------------------------
 template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
 __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.x == 0) {
+    step_head_block<D, T, S, NT>(a, reinterpret_cast<double*>(smem));
+    return;
+  }
   constexpr int NLOC = 2 * PPT;
   constexpr int PS = partial_stride(D);
   const int d = (int)a.d;
@@ -395,32 +515,28 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   T* xs = reinterpret_cast<T*>(smem + lc.take((size_t)d * E * sizeof(T)));
   T* scl = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   T* scu = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
-  int* sca = reinterpret_cast<int*>(smem + lc.take((size_t)C * P * sizeof(int)));
-  T* colw = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
-  T* red = reinterpret_cast<T*>(smem + lc.take((size_t)(NT / 64) * PS * sizeof(T)));
+  int* sca = reinterpret_cast<int*>(scu);  // positions overwrite the uniforms
+  const size_t red_bytes = (size_t)(NT / 64) * PS * sizeof(T);
+  T* red = reinterpret_cast<T*>(smem + lc.take(red_bytes > C * sizeof(T) ? red_bytes : C * sizeof(T)));
+  T* colw = red;  // carried weights live where the reduction scratch was
+  T* shx = reinterpret_cast<T*>(smem + lc.take((size_t)(D > NT / 64 ? D : NT / 64) * sizeof(T)));
   T* chm = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
   T* chs = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
   T* colm = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
   T* coltot = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
+  T* colu0 = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
 
-  const uint32_t tile = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t tile = xcd_tile(blockIdx.x - 1u, a.ntiles);
   const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
   const uint64_t N = a.N;
-  const T off = (T)a.ctl->offset;
-  T y[D], shift[D];
+  const T off = (T)read_offset(a.ctl, a.t);
+  T y[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
-    y[j] = 0;
-    shift[j] = 0;
-    if (j < d) {
-      y[j] = a.y_dev ? a.y_dev[j] : a.y_val[j];
-      shift[j] = (T)a.ctl->shift[j];
-    }
-  }
+  for (int j = 0; j < D; ++j) y[j] = (j < d) ? (a.y_dev ? a.y_dev[j] : a.y_val[j]) : (T)0;
   const uint32_t tau = a.t + 1u;
 
-  // ---- phase A: load, log-weight, randoms ---------------------------------
-  T lr[NLOC], xr[NLOC][D], zr[NLOC][D], lwn[NLOC];
+  // ---- phase A: load, log-weight, block-0 randoms -------------------------
+  T lr[NLOC], xr[NLOC][D], z0r[NLOC], lwn[NLOC];
   T tmax = -INFINITY;
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
@@ -432,7 +548,6 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       xr[2 * it][j] = xr[2 * it + 1][j] = 0;
-      zr[2 * it][j] = zr[2 * it + 1][j] = 0;
       if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + g0, xr[2 * it][j], xr[2 * it + 1][j]);
     }
     T w0, w1;
@@ -443,8 +558,7 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
     lr[2 * it + 1] = lwn[2 * it + 1] + Model<D, MK, T>::log_g(a.mp, xr[2 * it + 1], y);
     tmax = fmaxT(tmax, fmaxT(lr[2 * it], lr[2 * it + 1]));
     T u0, u1;
-    pair_randoms<D, T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, d, u0, u1, zr[2 * it],
-                       zr[2 * it + 1]);
+    pair_block0<T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, u0, u1, z0r[2 * it], z0r[2 * it + 1]);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       if (j < d) {
@@ -457,39 +571,63 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
     scu[c0 * P + q0] = u0;
     scu[c1 * P + q1] = u1;
   }
-  // estimate partials relative to the tile max
-  const T mtile = block_max<T, NT>(tmax, red);
-  T* prt = a.partials + (size_t)tile * PS;
-  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, shift, d, mtile, red, prt);
+  // tile reference point for the variance sums: the tile's first particle
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) shx[j] = xr[0][j];
+  }
+  const T mtile = block_max<T, NT>(tmax, red);  // (its barriers publish shx)
+  T sh[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) sh[j] = shx[j];
+  T* prt = a.part_out + (size_t)tile * PS;
+  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
   __syncthreads();
 
   // ---- phase B: group max / scan / carried weight / draw -------------------
   const bool sys = a.systematic != 0;
+  T tile_lwmax = -INFINITY;
   if (!BLOCKPATH) {
-    // r <= 64: a group is a segment of r lanes
+    // r <= 64: a group is a segment of r lanes; each wave handles 2 PPT
+    // tasks of 64 lanes, two of them interleaved at a time
     const uint32_t seg = lane & ~(r - 1u);
     const uint32_t q = lane & (r - 1u);
-    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
-      const uint32_t c = (task << (6 - log2r)) + (lane >> log2r);
-      const T l = scl[c * P + q];
-      T m = l;
-      for (uint32_t s = 1; s < r; s <<= 1) m = fmaxT(m, __shfl_xor(m, (int)s, 64));
-      T cdf = fexp(l - m);
-      for (uint32_t s = 1; s < r; s <<= 1) {
-        const T o = __shfl_up(cdf, s, 64);
-        if (q >= s) cdf += o;
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+      uint32_t c[2];
+      T l[2], m[2], cdf[2], tot[2], target[2];
+      uint32_t pos[2] = {0u, 0u};
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        const uint32_t task = wv + (2 * it + u) * (NT / 64);
+        c[u] = (task << (6 - log2r)) + (lane >> log2r);
+        l[u] = scl[c[u] * P + q];
       }
-      const T tot = __shfl(cdf, (int)(seg + r - 1u), 64);
-      const T u = scu[c * P + q];
-      const T u0 = __shfl(u, (int)seg, 64);
-      const T target = sys ? ((T)q + u0) * tot / (T)r : u * tot;
-      uint32_t pos = 0;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) m[u] = seg_max(l[u], log2r, lane);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) cdf[u] = seg_scan(fexp(l[u] - m[u]), log2r, q);
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        tot[u] = __shfl(cdf[u], (int)(seg + r - 1u), 64);
+        const T uu = scu[c[u] * P + q];
+        const T u0 = __shfl(uu, (int)seg, 64);
+        target[u] = sys ? ((T)q + u0) * tot[u] / (T)r : uu * tot[u];
+      }
       for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
-        const T v = __shfl(cdf, (int)(seg + pos + s - 1u), 64);
-        if (v <= target) pos += s;
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+          const T v = __shfl(cdf[u], (int)(seg + pos[u] + s - 1u), 64);
+          if (v <= target[u]) pos[u] += s;
+        }
       }
-      sca[c * P + q] = (int)pos;
-      if (q == 0) colw[c] = m + flog(tot) - a.lnr;
+#pragma unroll
+      for (int u = 0; u < 2; ++u) {
+        sca[c[u] * P + q] = (int)pos[u];
+        const T lw = m[u] + flog(tot[u]) - a.lnr;
+        tile_lwmax = fmaxT(tile_lwmax, lw);
+        if (q == 0) colw[c[u]] = lw;
+      }
     }
   } else {
     // r > 64: 64-member chunks, chunk maxima and sums through LDS
@@ -506,10 +644,13 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       T m = chm[c << lg_nch];
       for (uint32_t i = 1; i < nch; ++i) m = fmaxT(m, chm[(c << lg_nch) + i]);
       const uint32_t qq = (ch << 6) + lane;
-      const T cdf = wave_incl_scan(fexp(scl[c * P + qq] - m), lane);
+      const T cdf = seg_scan(fexp(scl[c * P + qq] - m), 6u, (uint32_t)lane);
       scl[c * P + qq] = cdf;
       if (lane == 63) chs[task] = cdf;
-      if (ch == 0 && lane == 0) colm[c] = m;
+      if (ch == 0 && lane == 0) {
+        colm[c] = m;
+        colu0[c] = scu[c * P];  // first member's uniform, before positions overwrite it
+      }
     }
     __syncthreads();
     for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
@@ -521,9 +662,13 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       }
       const uint32_t qq = (ch << 6) + lane;
       scl[c * P + qq] += offs;
-      if (ch == 0 && lane == 0) {
-        coltot[c] = tot;
-        colw[c] = colm[c] + flog(tot) - a.lnr;
+      if (ch == 0) {
+        const T lw = colm[c] + flog(tot) - a.lnr;
+        tile_lwmax = fmaxT(tile_lwmax, lw);
+        if (lane == 0) {
+          coltot[c] = tot;
+          colw[c] = lw;
+        }
       }
     }
     __syncthreads();
@@ -532,7 +677,7 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       const uint32_t qq = (ch << 6) + lane;
       const T tot = coltot[c];
       const T u = scu[c * P + qq];
-      const T target = sys ? ((T)qq + scu[c * P]) * tot / (T)r : u * tot;
+      const T target = sys ? ((T)qq + colu0[c]) * tot / (T)r : u * tot;
       uint32_t pos = 0;
       for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
         if (scl[c * P + pos + s - 1u] <= target) pos += s;
@@ -540,20 +685,28 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       sca[c * P + qq] = (int)pos;
     }
   }
+  // the next step's offset: max of the new log-weights (deterministic), one
+  // atomic per tile into one of the spread slots
+  tile_lwmax = wave_max(tile_lwmax);
+  if (lane == 0) shx[wv] = tile_lwmax;
   __syncthreads();
-  // max of the new log-weights of this tile -> partial slot 4
-  if (wv == 0) {
-    T mm = -INFINITY;
-    for (uint32_t c = lane; c < C; c += 64) mm = fmaxT(mm, colw[c]);
-    mm = wave_max(mm);
-    if (lane == 0) __hip_atomic_store(&prt[4], mm, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (tid == 0) {
+    T mx = shx[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) mx = fmaxT(mx, shx[w]);
+    __hip_atomic_fetch_max(off_slot(a.ctl, a.t + 1, tile % kOffSlots), ord_encode((double)mx),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  // ---- phase C: gather, propagate, store -----------------------------------
+  // ---- phase C: remaining normals, gather, propagate, store ----------------
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const uint32_t f0 = 2u * (tid + it * NT);
-    T xo[2][D], lwo[2];
+    T z[2][D], xo[2][D], lwo[2];
+#pragma unroll
+    for (int j = 0; j < D; ++j) z[0][j] = z[1][j] = 0;
+    z[0][0] = z0r[2 * it];
+    z[1][0] = z0r[2 * it + 1];
     uint64_t g0 = 0;
     uint32_t ai[2];
 #pragma unroll
@@ -561,12 +714,15 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       uint32_t q, c;
       uint64_t gi;
       tile_coords(geo, f0 + e, q, c, gi);
-      if (e == 0) g0 = gi;
+      if (e == 0) {
+        g0 = gi;
+        pair_normals_rest<D, T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
+      }
       const uint32_t pos = (uint32_t)sca[c * P + q];
       T xh[D];
 #pragma unroll
       for (int j = 0; j < D; ++j) xh[j] = (j < d) ? xs[(size_t)j * E + (pos << log2C) + c] : (T)0;
-      Model<D, MK, T>::propagate(a.mp, xh, zr[2 * it + e], xo[e]);
+      Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
       lwo[e] = colw[c];
       ai[e] = (uint32_t)((int64_t)gi + ((int64_t)pos - (int64_t)q) * ((int64_t)1 << a.log2R));
     }
@@ -579,55 +735,34 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       a.anc[g0 + 1] = ai[1];
     }
   }
-
-  // ---- tail: the last tile reduces every partial ---------------------------
-  // The partials were written with device-coherent stores; waiting for this
-  // thread's stores to complete before the barrier orders them before the
-  // ticket without an agent-scope fence (which would write back and
-  // invalidate the whole L2 of the XCD).
-  __shared__ uint32_t is_last;
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __builtin_amdgcn_s_waitcnt(0);
-  __atomic_signal_fence(__ATOMIC_SEQ_CST);
-  __syncthreads();
-  if (tid == 0) {
-    const uint32_t prev =
-        __hip_atomic_fetch_add(&a.ctl->counter, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    is_last = (prev == a.ntiles - 1u) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (is_last) {
-    finalize_partials<D, T, NT>(fin_args(a), a.partials, a.ntiles, reinterpret_cast<double*>(smem),
-                                true, true);
-  }
 }
 
 // ---------------------------------------------------------------------------
 // Global path, kernel 1: log-weights, tile max, tile inclusive CDF and
-// estimate partials. Every thread owns NLOC contiguous particles.
+// estimate partials. Every thread owns NLOC contiguous particles. Block 0
+// is the head block (previous step's reduction).
 // ---------------------------------------------------------------------------
 template <int D, int MK, typename T, typename S, int NT, int PPT>
 __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   constexpr int NLOC = 2 * PPT;
   constexpr int PS = partial_stride(D);
   constexpr uint32_t E = 2u * NT * PPT;
+  __shared__ double fin_red[(NT / 64) * (4 + 2 * D)];
   __shared__ T red[(NT / 64) * PS];
   __shared__ T wtot[NT / 64];
+  __shared__ T shx[D];
+  if (blockIdx.x == 0) {
+    step_head_block<D, T, S, NT>(a, fin_red);
+    return;
+  }
   const int d = (int)a.d;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t tile = blockIdx.x;
+  const uint32_t tile = blockIdx.x - 1u;
   const uint64_t base = (uint64_t)tile * E + (uint64_t)tid * NLOC;
   const uint64_t N = a.N;
-  T y[D], shift[D];
+  T y[D];
 #pragma unroll
-  for (int j = 0; j < D; ++j) {
-    y[j] = 0;
-    shift[j] = 0;
-    if (j < d) {
-      y[j] = a.y_dev ? a.y_dev[j] : a.y_val[j];
-      shift[j] = (T)a.ctl->shift[j];
-    }
-  }
+  for (int j = 0; j < D; ++j) y[j] = (j < d) ? (a.y_dev ? a.y_dev[j] : a.y_val[j]) : (T)0;
   T lr[NLOC], xr[NLOC][D], lwn[NLOC];
   T tmax = -INFINITY;
 #pragma unroll
@@ -641,7 +776,7 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     if (a.lw_nonzero) {
       T w0, w1;
       Pair<T, T>::load(a.lw_in + base + e, w0, w1);
-      const T off = (T)a.ctl->offset;
+      const T off = (T)read_offset(a.ctl, a.t);
       lwn[e] = w0 - off;
       lwn[e + 1] = w1 - off;
     }
@@ -649,7 +784,14 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     lr[e + 1] = lwn[e + 1] + Model<D, MK, T>::log_g(a.mp, xr[e + 1], y);
     tmax = fmaxT(tmax, fmaxT(lr[e], lr[e + 1]));
   }
+  if (tid == 0) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) shx[j] = xr[0][j];
+  }
   const T mtile = block_max<T, NT>(tmax, red);
+  T sh[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) sh[j] = shx[j];
   // inclusive CDF of e^{l - mtile} over the tile, in particle order
   T w[NLOC];
   T run = 0;
@@ -674,26 +816,23 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     a.gcdf[base + e] = c;
     if (((tid * NLOC + e) & 63) == 63) a.gcoarse[(base + e) >> 6] = c;
   }
-  T* prt = a.partials + (size_t)tile * PS;
-  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, shift, d, mtile, red, prt);
+  T* prt = a.part_out + (size_t)tile * PS;
+  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
   __syncthreads();
-  if (tid == 0) {
-    prt[1] = tot;  // the tile's weight sum is the CDF total (same rounding as the CDF)
-    prt[4] = 0;
-  }
+  if (tid == 0) prt[1] = tot;  // the tile's weight sum is the CDF total (same rounding as the CDF)
 }
 
-// Global path, kernel 2 (one block): tile prefix in FP64 and the finalize.
+// Global path, kernel 2 (one block): tile prefix in FP64; every new
+// log-weight is equal, so the next offset is 0.
 template <int D, typename T, typename S, int NT>
 __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  double* sd = reinterpret_cast<double*>(smem);
+  __shared__ double sd[NT];
   constexpr int PS = partial_stride(D);
+  const T* part = a.part_out;
   const uint32_t nt = a.ntiles;
   const int tid = threadIdx.x;
-  // global max of the tile maxima
   double m = -INFINITY;
-  for (uint32_t b = tid; b < nt; b += NT) m = fmax(m, (double)a.partials[(size_t)b * PS]);
+  for (uint32_t b = tid; b < nt; b += NT) m = fmax(m, (double)part[(size_t)b * PS]);
   sd[tid] = m;
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
@@ -707,13 +846,12 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   const uint32_t b0 = tid * per, b1 = min(nt, b0 + per);
   double loc = 0.0;
   for (uint32_t b = b0; b < b1; ++b) {
-    const double e = exp((double)a.partials[(size_t)b * PS] - M);
+    const double e = exp((double)part[(size_t)b * PS] - M);
     a.gscale[b] = e;
-    loc += e * (double)a.partials[(size_t)b * PS + 1];
+    loc += e * (double)part[(size_t)b * PS + 1];
   }
   sd[tid] = loc;
   __syncthreads();
-  // Hillis-Steele over thread totals (fixed order)
   for (int s = 1; s < NT; s <<= 1) {
     const double o = tid >= s ? sd[tid - s] : 0.0;
     __syncthreads();
@@ -723,12 +861,10 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   double run = sd[tid] - loc;
   for (uint32_t b = b0; b < b1; ++b) {
     a.gpre[b] = run;
-    run += a.gscale[b] * (double)a.partials[(size_t)b * PS + 1];
+    run += a.gscale[b] * (double)part[(size_t)b * PS + 1];
   }
   if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
-  __syncthreads();
-  finalize_partials<D, T, NT>(fin_args(a), a.partials, nt, sd, false, false);
-  if (tid == 0) a.ctl->offset = 0.0;  // every new log-weight is equal: renormalised to 0
+  if (tid == 0) *off_slot(a.ctl, a.t + 1, 0) = ord_encode(0.0);
 }
 
 // Global path, kernel 3: inverse-CDF draw over the whole population (tile

@@ -14,7 +14,8 @@ enum LaunchWhat : int {
   LW_STEP_TILE = 1,
   LW_GLOBAL_WEIGHT = 2,
   LW_GLOBAL_PREFIX = 3,
-  LW_GLOBAL_DRAW = 4
+  LW_GLOBAL_DRAW = 4,
+  LW_FINALIZE = 5
 };
 
 // What the runtime asks for.
@@ -28,6 +29,10 @@ struct LaunchReq {
   uint32_t grid;
   size_t lds;    // dynamic LDS bytes
   uint32_t tile_elems;  // global draw: particles per weight tile
+  // finalize (LW_FINALIZE): the step whose partials are reduced
+  FinArgs fin;
+  const void* fin_part;
+  uint32_t fin_ntiles;
 };
 
 // Pairs per thread of the butterfly wave path (256 threads) by dimension:
@@ -117,6 +122,11 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(1), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    case LW_FINALIZE: {
+      hipLaunchKernelGGL((pf_finalize_kernel<D, T, 256>), dim3(1), dim3(256), 0, st, rq.fin,
+                         reinterpret_cast<const T*>(rq.fin_part), rq.fin_ntiles);
       return hipGetLastError();
     }
     case LW_GLOBAL_DRAW: {

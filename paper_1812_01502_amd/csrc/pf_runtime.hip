@@ -52,7 +52,10 @@ struct pf_handle {
   void* lw[2] = {nullptr, nullptr};
   int cur = 0;
   void* mp = nullptr;        // ModelParams<T>
-  void* partials = nullptr;
+  void* partials[2] = {nullptr, nullptr};  // tile partials by step parity
+  // the last step whose partials have not been reduced yet
+  bool fin_pending = false;
+  uint32_t pend_t = 0, pend_k = 0, pend_radix = 0, pend_ntiles = 0;
   Ctl* ctl = nullptr;
   pf_estimate_t* hist = nullptr;
   uint32_t hist_cap = 1;
@@ -245,7 +248,14 @@ template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>&
   a.lw_out = reinterpret_cast<T*>(h->lw[h->cur ^ 1]);
   a.anc = h->anc;
   a.mp = reinterpret_cast<const ModelParams<T>*>(h->mp);
-  a.partials = reinterpret_cast<T*>(h->partials);
+  a.part_out = reinterpret_cast<T*>(h->partials[h->t & 1]);
+  if (h->fin_pending) {
+    a.part_prev = reinterpret_cast<const T*>(h->partials[h->pend_t & 1]);
+    a.ntiles_prev = h->pend_ntiles;
+    a.t_prev = h->pend_t;
+    a.k_prev = h->pend_k;
+    a.radix_prev = h->pend_radix;
+  }
   a.ctl = h->ctl;
   a.hist = h->hist;
   a.hist_cap = h->hist_cap;
@@ -280,6 +290,7 @@ pf_status run_init(pf_handle* h) {
   if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
   h->t = 0;
   h->lw_zero = true;
+  h->fin_pending = false;
   return PF_OK;
 }
 
@@ -314,7 +325,7 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.nt = sp.nt;
     rq.ppt = sp.ppt;
     rq.blockpath = sp.blockpath;
-    rq.grid = sp.ntiles;
+    rq.grid = sp.ntiles + 1;  // block 0 reduces the previous step
     rq.lds = sp.lds;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
@@ -327,13 +338,13 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.what = LW_GLOBAL_WEIGHT;
     rq.nt = (int)h->g_nt;
     rq.ppt = (int)h->g_ppt;
-    rq.grid = h->g_ntiles;
+    rq.grid = h->g_ntiles + 1;  // block 0 reduces the previous step
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global weight launch");
     rq.what = LW_GLOBAL_PREFIX;
     rq.nt = 256;
     rq.grid = 1;
-    rq.lds = std::max<size_t>(256 * 8, (size_t)4 * partial_stride(h->D) * 8);
+    rq.lds = 0;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global prefix launch");
     rq.what = LW_GLOBAL_DRAW;
@@ -349,7 +360,38 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
   // the global path does not store log-weights: after it every one is 0
   h->cur ^= 1;
   h->lw_zero = h->global;
+  h->fin_pending = true;
+  h->pend_t = (uint32_t)h->t;
+  h->pend_k = k;
+  h->pend_radix = h->global ? (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu) : sp.r;
+  h->pend_ntiles = h->global ? h->g_ntiles : sp.ntiles;
   h->t += 1;
+  return PF_OK;
+}
+
+// Reduce the last step's partials (estimate record, log-normaliser).
+pf_status flush(pf_handle* h) {
+  if (!h->fin_pending) return PF_OK;
+  LaunchReq rq{};
+  rq.what = LW_FINALIZE;
+  rq.D = h->D;
+  rq.mk = h->mk;
+  rq.grid = 1;
+  rq.fin.ctl = h->ctl;
+  rq.fin.hist = h->hist;
+  rq.fin.hist_cap = h->hist_cap;
+  rq.fin.t = h->pend_t;
+  rq.fin.k = h->pend_k;
+  rq.fin.radix = h->pend_radix;
+  rq.fin.d = (uint32_t)h->d;
+  rq.fin.N = h->N;
+  rq.fin_part = h->partials[h->pend_t & 1];
+  rq.fin_ntiles = h->pend_ntiles;
+  // any StepArgs will do for the dispatch; only the request is read
+  char dummy[sizeof(StepArgs<double, double>)] = {0};
+  hipError_t e = launch(h, rq, dummy);
+  if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+  h->fin_pending = false;
   return PF_OK;
 }
 
@@ -570,7 +612,9 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   }
   uint32_t max_tiles = h->global ? h->g_ntiles : 0;
   for (auto& sp : h->stages) max_tiles = std::max(max_tiles, sp.ntiles);
-  if ((s = dalloc(h, &h->partials, (size_t)max_tiles * partial_stride(h->D) * h->tsz)) != PF_OK) return bail(s);
+  for (int i = 0; i < 2; ++i)
+    if ((s = dalloc(h, &h->partials[i], (size_t)max_tiles * partial_stride(h->D) * h->tsz)) != PF_OK)
+      return bail(s);
   void* p = nullptr;
   if ((s = dalloc(h, &p, sizeof(Ctl))) != PF_OK) return bail(s);
   h->ctl = reinterpret_cast<Ctl*>(p);
@@ -642,6 +686,7 @@ pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_s
   pf_status st = PF_OK;
   for (uint32_t j = 0; j < n_steps && st == PF_OK; ++j)
     st = do_step(h, nullptr, yb + (size_t)j * y_stride * h->tsz);
+  if (st == PF_OK) st = flush(h);
   if (use_graph) {
     hipError_t e = hipStreamEndCapture(h->stream, &graph);
     if (st != PF_OK) {
@@ -667,6 +712,10 @@ pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_s
 
 pf_status pf_sync(pf_handle* h) {
   if (!h) return PF_E_INVALID;
+  if (!poisoned(h)) {
+    pf_status fs = flush(h);
+    if (fs != PF_OK) return fs;
+  }
   hipError_t e = h->stream ? hipStreamSynchronize(h->stream) : hipDeviceSynchronize();
   if (e != hipSuccess) return hip_fail(h, e, "synchronize");
   return PF_OK;
@@ -721,12 +770,15 @@ pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_
     e = hipMemcpy(logw_host, h->lw[h->cur], (size_t)h->N * h->tsz, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return hip_fail(h, e, "log-weight copy");
     // stored log-weights are normalised by the offset the next step would subtract
+    double off = -INFINITY;
+    for (int sl = 0; sl < kOffSlots; ++sl)
+      off = std::max(off, ord_decode(c.offs[(h->t % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
     if (h->tsz == 8) {
       double* w = reinterpret_cast<double*>(logw_host);
-      for (uint64_t i = 0; i < h->N; ++i) w[i] -= c.offset;
+      for (uint64_t i = 0; i < h->N; ++i) w[i] -= off;
     } else {
       float* w = reinterpret_cast<float*>(logw_host);
-      const float o = (float)c.offset;
+      const float o = (float)off;
       for (uint64_t i = 0; i < h->N; ++i) w[i] -= o;
     }
   }
@@ -753,11 +805,11 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   Ctl c;
   e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "control copy");
-  c.offset = 0.0;
   c.log_norm = log_norm;
-  c.counter = 0;
+  for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
+  c.offs[(t % kOffRing) * kOffSlots * kOffStride] = ord_encode(0.0);
   c.t = t;
-  for (int j = 0; j < kMaxDim; ++j) c.shift[j] = 0.0;
+  h->fin_pending = false;
   e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "control upload");
   h->t = t;
