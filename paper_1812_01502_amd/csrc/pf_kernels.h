@@ -178,6 +178,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = (int)f.d;
   double m = -INFINITY;
+#pragma unroll 4
   for (uint32_t b = tid; b < ntiles; b += NT) m = fmax(m, (double)part[(size_t)b * PS]);
   m = wave_max_d(m);
   if (lane == 0) red[wv] = m;
@@ -188,6 +189,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
   double acc[NV];
 #pragma unroll
   for (int v = 0; v < NV; ++v) acc[v] = 0.0;
+#pragma unroll 4
   for (uint32_t b = tid; b < ntiles; b += NT) {
     const T* pr = part + (size_t)b * PS;
     const double e = exp((double)pr[0] - M);
@@ -536,40 +538,38 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   const uint32_t tau = a.t + 1u;
 
   // ---- phase A: load, log-weight, block-0 randoms -------------------------
-  T lr[NLOC], xr[NLOC][D], z0r[NLOC], lwn[NLOC];
-  T tmax = -INFINITY;
+  // all loads are issued first; the block-0 randoms (independent of them)
+  // are drawn while they are in flight
+  T lr[NLOC], xr[NLOC][D], z0r[NLOC], lwn[NLOC], ur[NLOC];
+  uint32_t qa[NLOC], ca[NLOC];
+  uint64_t ga[PPT];
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
-    const uint32_t f0 = 2u * (tid + it * NT);
-    uint32_t q0, c0, q1, c1;
-    uint64_t g0, g1;
-    tile_coords(geo, f0, q0, c0, g0);
-    tile_coords(geo, f0 + 1, q1, c1, g1);
+    uint64_t g1;
+    tile_coords(geo, 2u * (tid + it * NT), qa[2 * it], ca[2 * it], ga[it]);
+    tile_coords(geo, 2u * (tid + it * NT) + 1, qa[2 * it + 1], ca[2 * it + 1], g1);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       xr[2 * it][j] = xr[2 * it + 1][j] = 0;
-      if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + g0, xr[2 * it][j], xr[2 * it + 1][j]);
+      if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + ga[it], xr[2 * it][j], xr[2 * it + 1][j]);
     }
-    T w0, w1;
-    Pair<T, T>::load(a.lw_in + g0, w0, w1);
-    lwn[2 * it] = w0 - off;
-    lwn[2 * it + 1] = w1 - off;
-    lr[2 * it] = lwn[2 * it] + Model<D, MK, T>::log_g(a.mp, xr[2 * it], y);
-    lr[2 * it + 1] = lwn[2 * it + 1] + Model<D, MK, T>::log_g(a.mp, xr[2 * it + 1], y);
-    tmax = fmaxT(tmax, fmaxT(lr[2 * it], lr[2 * it + 1]));
-    T u0, u1;
-    pair_block0<T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, u0, u1, z0r[2 * it], z0r[2 * it + 1]);
+    Pair<T, T>::load(a.lw_in + ga[it], lwn[2 * it], lwn[2 * it + 1]);
+  }
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      if (j < d) {
-        xs[(size_t)j * E + (q0 << log2C) + c0] = xr[2 * it][j];
-        xs[(size_t)j * E + (q1 << log2C) + c1] = xr[2 * it + 1][j];
-      }
-    }
-    scl[c0 * P + q0] = lr[2 * it];
-    scl[c1 * P + q1] = lr[2 * it + 1];
-    scu[c0 * P + q0] = u0;
-    scu[c1 * P + q1] = u1;
+  for (int it = 0; it < PPT; ++it)
+    pair_block0<T>((uint32_t)(ga[it] >> 1), tau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
+                   z0r[2 * it], z0r[2 * it + 1]);
+  T tmax = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < NLOC; ++e) {
+    lwn[e] -= off;
+    lr[e] = lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y);
+    tmax = fmaxT(tmax, lr[e]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) xs[(size_t)j * E + (qa[e] << log2C) + ca[e]] = xr[e][j];
+    scl[ca[e] * P + qa[e]] = lr[e];
+    scu[ca[e] * P + qa[e]] = ur[e];
   }
   // tile reference point for the variance sums: the tile's first particle
   if (tid == 0) {
@@ -589,26 +589,28 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   T tile_lwmax = -INFINITY;
   if (!BLOCKPATH) {
     // r <= 64: a group is a segment of r lanes; each wave handles 2 PPT
-    // tasks of 64 lanes, two of them interleaved at a time
+    // tasks of 64 lanes, U of them interleaved at a time
+    constexpr int U = (2 * PPT) < 4 ? (2 * PPT) : 4;
     const uint32_t seg = lane & ~(r - 1u);
     const uint32_t q = lane & (r - 1u);
 #pragma unroll
-    for (int it = 0; it < PPT; ++it) {
-      uint32_t c[2];
-      T l[2], m[2], cdf[2], tot[2], target[2];
-      uint32_t pos[2] = {0u, 0u};
+    for (int it = 0; it < (2 * PPT) / U; ++it) {
+      uint32_t c[U];
+      T l[U], m[U], cdf[U], tot[U], target[U];
+      uint32_t pos[U];
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
-        const uint32_t task = wv + (2 * it + u) * (NT / 64);
+      for (int u = 0; u < U; ++u) {
+        const uint32_t task = wv + (U * it + u) * (NT / 64);
         c[u] = (task << (6 - log2r)) + (lane >> log2r);
         l[u] = scl[c[u] * P + q];
+        pos[u] = 0u;
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) m[u] = seg_max(l[u], log2r, lane);
+      for (int u = 0; u < U; ++u) m[u] = seg_max(l[u], log2r, lane);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) cdf[u] = seg_scan(fexp(l[u] - m[u]), log2r, q);
+      for (int u = 0; u < U; ++u) cdf[u] = seg_scan(fexp(l[u] - m[u]), log2r, q);
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < U; ++u) {
         tot[u] = __shfl(cdf[u], (int)(seg + r - 1u), 64);
         const T uu = scu[c[u] * P + q];
         const T u0 = __shfl(uu, (int)seg, 64);
@@ -616,13 +618,13 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       }
       for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
 #pragma unroll
-        for (int u = 0; u < 2; ++u) {
+        for (int u = 0; u < U; ++u) {
           const T v = __shfl(cdf[u], (int)(seg + pos[u] + s - 1u), 64);
           if (v <= target[u]) pos[u] += s;
         }
       }
 #pragma unroll
-      for (int u = 0; u < 2; ++u) {
+      for (int u = 0; u < U; ++u) {
         sca[c[u] * P + q] = (int)pos[u];
         const T lw = m[u] + flog(tot[u]) - a.lnr;
         tile_lwmax = fmaxT(tile_lwmax, lw);

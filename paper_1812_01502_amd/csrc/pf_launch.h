@@ -38,6 +38,9 @@ struct LaunchReq {
 // Pairs per thread of the butterfly wave path (256 threads) by dimension:
 // keeps the registers held across the step (states, normals) bounded.
 constexpr int ppt_wave(int D) { return D <= 2 ? 4 : (D <= 8 ? 2 : 1); }
+// Pairs per thread of the butterfly block path (256 threads): tiles of
+// 512 PPT particles hold at least two groups of r <= 256 PPT.
+constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 : 1)); }
 // Pairs per thread of the global weight kernel (256 threads).
 constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
 constexpr int kDrawPPT = 4;
@@ -72,6 +75,22 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
           return hipGetLastError();
         }
         return hipErrorInvalidValue;
+      }
+      if (rq.nt == 256 && rq.ppt == ppt_block(D)) {
+        auto k = pf_step_tile<D, MK, T, S, 256, ppt_block(D), true>;
+        hipError_t e = ensure_lds(k, rq.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+        return hipGetLastError();
+      }
+      if constexpr (D <= 2) {
+        if (rq.nt == 256 && rq.ppt == 4) {
+          auto k = pf_step_tile<D, MK, T, S, 256, 4, true>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+          return hipGetLastError();
+        }
       }
       if (rq.nt == 256 && rq.ppt == 1) {
         auto k = pf_step_tile<D, MK, T, S, 256, 1, true>;

@@ -461,7 +461,16 @@ pf_status plan_stages(pf_handle* h) {
       }
     } else {
       sp.blockpath = 1;
-      if (sp.r <= 1024 && N >= 2048) {
+      // 256-thread tiles of at least two groups; larger tiles give longer
+      // contiguous rows at wide strides
+      const uint32_t pb = (uint32_t)ppt_block(h->D);
+      if (h->D <= 2 && sp.r <= 256 && N >= 2048u) {
+        sp.nt = 256;
+        sp.ppt = 4;
+      } else if (512u * pb >= 2u * sp.r && 512u * pb <= N) {
+        sp.nt = 256;
+        sp.ppt = (int)pb;
+      } else if (sp.r <= 1024 && N >= 2048) {
         sp.nt = 1024;
         sp.ppt = 1;
       } else if (sp.r <= 256) {
