@@ -74,13 +74,17 @@ def count_le(C: np.ndarray, tgt: np.ndarray) -> np.ndarray:
     return out
 
 
-def group_resample(ell: np.ndarray, U: np.ndarray, r: int, R: int, resampler: str):
+def group_resample(ell: np.ndarray, U: np.ndarray, r: int, R: int, resampler: str,
+                   detail: bool = False):
     """One butterfly stage on log-weights ``ell`` (shape ``(N,)``).
 
     Groups are the ``r`` indices ``h r R + q R + lo`` (``q = 0..r-1``).
     Returns ``(ancestor index (N,), new log-weight (N,), margin (N,))``;
     ``margin`` is the distance from the draw's target to the nearest
-    cumulative weight, relative to the group total.
+    cumulative weight, relative to the group total. With ``detail`` a fourth
+    item gives, per destination, the draw's target and the cumulative
+    weights bounding every member's interval (``cdf[i, q]`` is
+    ``c_q`` of destination i's group), all relative to the group total.
     """
     N = ell.shape[0]
     nh = N // (r * R)
@@ -111,7 +115,14 @@ def group_resample(ell: np.ndarray, U: np.ndarray, r: int, R: int, resampler: st
     anc = np.arange(N, dtype=np.int64) + anc_off
     new_lw = np.broadcast_to(new_lw, (l2.shape[0], r)).reshape(shape3).transpose(0, 2, 1).reshape(N)
     margin = margin.reshape(shape3).transpose(0, 2, 1).reshape(N)
-    return anc, np.ascontiguousarray(new_lw), np.ascontiguousarray(margin)
+    if not detail:
+        return anc, np.ascontiguousarray(new_lw), np.ascontiguousarray(margin)
+    # per destination (index order): its group's row in (groups, members) form
+    row = (np.arange(l2.shape[0]).reshape(nh, R)[:, None, :]
+           * np.ones((1, r, 1), dtype=np.int64)).reshape(N)
+    tgt_i = (tgt / total).reshape(shape3).transpose(0, 2, 1).reshape(N)
+    info = dict(row=row, target=tgt_i, cdf=C / total)
+    return anc, np.ascontiguousarray(new_lw), np.ascontiguousarray(margin), info
 
 
 def weighted_estimate(x: np.ndarray, ell: np.ndarray, logw: np.ndarray):
@@ -163,7 +174,10 @@ class ButterflyOracle:
         ell = st.logw + models.log_g(self.model, st.x, y)
         est = weighted_estimate(st.x, ell, st.logw)
         U = philox.resample_uniforms(self.seed, self.stream_id, tau, self.N)
-        anc, new_lw, margin = group_resample(ell, U, r, R, self.resampler)
+        if keep:
+            anc, new_lw, margin, info = group_resample(ell, U, r, R, self.resampler, detail=True)
+        else:
+            anc, new_lw, margin = group_resample(ell, U, r, R, self.resampler)
         xhat = st.x[anc]
         c = np.max(new_lw)
         logw = new_lw - c
@@ -174,7 +188,7 @@ class ButterflyOracle:
                    var=est["var"], ess=est["ess"], log_norm=log_norm,
                    max_ell=est["max_ell"], offset=float(c))
         if keep:
-            rec.update(ancestors=anc, margin=margin, logw_new=new_lw, ell=ell)
+            rec.update(ancestors=anc, margin=margin, logw_new=new_lw, ell=ell, draw=info)
         return State(x=x, logw=logw, t=t + 1, log_norm=log_norm), rec
 
     def run(self, ys, keep=False, state: State | None = None):

@@ -85,6 +85,18 @@ def compare_one_step(flt, orc: ButterflyOracle, x_or: np.ndarray, logw_or: np.nd
     r, R = rec_o["radix"], rec_o["stride"]
     i = np.arange(N)
     assert np.array_equal((anc_g // (r * R), anc_g % R), (i // (r * R), i % R)) or r == N
+    # a tolerated flip must still be a valid draw: the target lies within the
+    # margin of the device ancestor's own cumulative-weight interval
+    if np.any(mism):
+        dr = rec_o["draw"]
+        idx = np.nonzero(mism)[0]
+        qg = (anc_g[idx] // R) % r
+        rows = dr["row"][idx]
+        hi = dr["cdf"][rows, qg]
+        lo = np.where(qg > 0, dr["cdf"][rows, np.maximum(qg - 1, 0)], 0.0)
+        tg = dr["target"][idx]
+        ok_int = (tg >= lo - MARGIN_TOL) & (tg <= hi + MARGIN_TOL)
+        assert np.all(ok_int), (label, "flip outside the ancestor's interval", idx[~ok_int][:8])
     # new log-weights (normalised so that the max is 0)
     dw = np.abs(wg.astype(np.float64) - st_o.logw)
     assert np.max(dw) <= tol["w_atol"], (label, "logw", float(np.max(dw)))
