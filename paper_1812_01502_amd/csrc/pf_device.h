@@ -370,15 +370,43 @@ __device__ __forceinline__ float wave_max(float v) {
   v = fmaxf(v, b31);
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), 63));
 }
+// FP64 lane moves: the two 32-bit halves move with the same DPP control.
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ double dpp_d(double v) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)b, CTRL, ROW_MASK, 0xF, false);
+  const unsigned hi =
+      (unsigned)__builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, ROW_MASK, 0xF, false);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
+__device__ __forceinline__ double readlane_d(double v, int l) {
+  const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __builtin_bit_cast(double, ((unsigned long long)hi << 32) | lo);
+}
 __device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
-  return v;
+  v += dpp_d<kDppQuadXor1>(v);
+  v += dpp_d<kDppQuadXor2>(v);
+  v += dpp_d<kDppRowHalfMirror>(v);
+  v += dpp_d<kDppRowMirror>(v);
+  v += dpp_d<kDppRowBcast15, 0xA>(v);
+  v += dpp_d<kDppRowBcast31, 0xC>(v);
+  return readlane_d(v, 63);
 }
 __device__ __forceinline__ double wave_max(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
-  return v;
+  v = fmax(v, dpp_d<kDppQuadXor1>(v));
+  v = fmax(v, dpp_d<kDppQuadXor2>(v));
+  v = fmax(v, dpp_d<kDppRowHalfMirror>(v));
+  v = fmax(v, dpp_d<kDppRowMirror>(v));
+  const int lane = __lane_id();
+  double b15 = dpp_d<kDppRowBcast15, 0xA>(v);
+  if (((lane >> 4) & 1) == 0) b15 = v;
+  v = fmax(v, b15);
+  double b31 = dpp_d<kDppRowBcast31, 0xC>(v);
+  if ((lane >> 5) == 0) b31 = v;
+  v = fmax(v, b31);
+  return readlane_d(v, 63);
 }
 // Inclusive prefix sum over the 64 lanes.
 template <typename T> __device__ __forceinline__ T wave_incl_scan(T v, int lane) {

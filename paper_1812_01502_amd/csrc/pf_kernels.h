@@ -150,104 +150,152 @@ struct FinArgs {
   uint64_t N;
 };
 
-__device__ __forceinline__ double wave_sum_d(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v += __shfl_xor(v, s, 64);
-  return v;
-}
-__device__ __forceinline__ double wave_max_d(double v) {
-#pragma unroll
-  for (int s = 32; s >= 1; s >>= 1) v = fmax(v, __shfl_xor(v, s, 64));
-  return v;
+// FP64 reduction of one step's tile partials by one block, in a fixed order.
+// Partial record of tile b: [m, S, sw2, swin, A1[D], A2[D], sh[D]] with m the
+// tile max of l, w = e^{l - m}, S = sum w, sw2 = sum w^2, swin = sum e^{logW},
+// A1 = sum w (x - sh), A2 = sum w (x - sh)^2, sh a tile reference point.
+// Thread i takes tiles i, i + NT, ... in rounds of FB tiles whose loads are
+// all issued before any is used (one memory round trip per round: the
+// stand-alone kernel uses large rounds, the head block of a step kernel
+// single tiles so that it needs no more registers than the tiles); sums are
+// kept relative to the thread's running max and rescaled when it grows.
+// Waves reduce with DPP in a fixed pattern; wave 0 combines the waves in wave
+// order, one value per lane. Writes the estimate record of step f.t and adds
+// its log-normaliser increment. `red` needs (NT/64) * (4 + 2D) doubles.
+template <int D, typename T> constexpr int fin_batch() {
+  constexpr int dw = (int)(partial_stride(D) * sizeof(T) / 4);  // registers per record
+  constexpr int b = 64 / dw;
+  return b < 1 ? 1 : (b > 8 ? 8 : b);
 }
 
-// FP64 reduction of one step's tile partials by one block, in a fixed order
-// (thread i takes tiles i, i + NT, ...; waves reduce by a fixed butterfly;
-// wave results are added in wave order). Partial record of tile b:
-// [m, S, sw2, swin, A1[D], A2[D], sh[D]] with m the tile max of l,
-// w = e^{l - m}, S = sum w, sw2 = sum w^2, swin = sum e^{logW},
-// A1 = sum w (x - sh), A2 = sum w (x - sh)^2, sh a tile reference point.
-// Writes the estimate record of step f.t and adds its log-normaliser
-// increment. `red` needs (NT/64) * (4 + 2D) doubles.
-template <int D, typename T, int NT>
+template <int D, typename T, int NT, int FB>
 __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, uint32_t ntiles,
                                   double* red) {
   constexpr int PS = partial_stride(D);
-  constexpr int NV = 4 + 2 * D;  // accumulated values: m(unused), S, sw2, swin, Mx[D], Mxx[D]
+  constexpr int NR = 4 + 2 * D;  // per wave: [M_w, swin, S, sw2, Mx[D], Mxx[D]]
   constexpr int NW = NT / 64;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int d = (int)f.d;
-  double m = -INFINITY;
-#pragma unroll 4
-  for (uint32_t b = tid; b < ntiles; b += NT) m = fmax(m, (double)part[(size_t)b * PS]);
-  m = wave_max_d(m);
-  if (lane == 0) red[wv] = m;
-  __syncthreads();
-  double M = red[0];
-  for (int w = 1; w < NW; ++w) M = fmax(M, red[w]);
-  __syncthreads();
-  double acc[NV];
+  // wave 0 fetches the next step's offset slots and the running normaliser
+  // up front: they are only needed at the end
+  double offv = -INFINITY, ln0 = 0.0;
+  if (wv == 0) {
+    if (lane < kOffSlots) offv = ord_decode(*off_slot(f.ctl, f.t + 1, lane));
+    if (lane == 0) ln0 = f.ctl->log_norm;
+  }
+  double mt = -INFINITY, swin = 0.0, s = 0.0, sw2 = 0.0, a1[D], a2[D];
 #pragma unroll
-  for (int v = 0; v < NV; ++v) acc[v] = 0.0;
-#pragma unroll 4
-  for (uint32_t b = tid; b < ntiles; b += NT) {
-    const T* pr = part + (size_t)b * PS;
-    const double e = exp((double)pr[0] - M);
-    const double Sb = (double)pr[1];
-    acc[1] += e * Sb;
-    acc[2] += e * e * (double)pr[2];
-    acc[3] += (double)pr[3];
+  for (int j = 0; j < D; ++j) a1[j] = a2[j] = 0.0;
+  for (uint32_t b0 = tid; b0 < ntiles; b0 += NT * FB) {
+    T rec[FB][PS];
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      if (j < d) {
-        const double a1 = (double)pr[4 + j], a2 = (double)pr[4 + D + j], s = (double)pr[4 + 2 * D + j];
-        acc[4 + j] += e * (a1 + Sb * s);
-        acc[4 + D + j] += e * (a2 + 2.0 * s * a1 + Sb * s * s);
+    for (int q = 0; q < FB; ++q) {
+      const uint32_t b = b0 + (uint32_t)q * NT;
+      const T* pr = part + (size_t)(b < ntiles ? b : 0) * PS;
+#pragma unroll
+      for (int v = 0; v < PS; ++v) rec[q][v] = pr[v];
+    }
+    double mr = mt;
+#pragma unroll
+    for (int q = 0; q < FB; ++q)
+      if (b0 + (uint32_t)q * NT < ntiles) mr = fmax(mr, (double)rec[q][0]);
+    if (mr > mt) {
+      const double sc = mt == -INFINITY ? 0.0 : exp(mt - mr);
+      s *= sc;
+      sw2 *= sc * sc;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        a1[j] *= sc;
+        a2[j] *= sc;
+      }
+      mt = mr;
+    }
+#pragma unroll
+    for (int q = 0; q < FB; ++q) {
+      if (b0 + (uint32_t)q * NT >= ntiles) continue;
+      const double mb = (double)rec[q][0];
+      const double e = mb == -INFINITY ? 0.0 : exp(mb - mt);
+      const double Sb = (double)rec[q][1];
+      s += e * Sb;
+      sw2 += e * e * (double)rec[q][2];
+      swin += (double)rec[q][3];
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        if (j < d) {
+          const double c1 = (double)rec[q][4 + j], c2 = (double)rec[q][4 + D + j];
+          const double sh = (double)rec[q][4 + 2 * D + j];
+          a1[j] += e * (c1 + Sb * sh);
+          a2[j] += e * (c2 + 2.0 * sh * c1 + Sb * sh * sh);
+        }
       }
     }
   }
+  // wave level: common max, then fixed-pattern sums
+  const double Mw = wave_max(mt);
+  {
+    const double sc = (mt == -INFINITY) ? 0.0 : exp(mt - Mw);
+    s = wave_sum(s * sc);
+    sw2 = wave_sum(sw2 * (sc * sc));
+    swin = wave_sum(swin);
 #pragma unroll
-  for (int v = 1; v < NV; ++v) {
-    if ((v >= 4 + d && v < 4 + D) || v >= 4 + D + d) continue;
-    acc[v] = wave_sum_d(acc[v]);
+    for (int j = 0; j < D; ++j) {
+      if (j < d) {
+        a1[j] = wave_sum(a1[j] * sc);
+        a2[j] = wave_sum(a2[j] * sc);
+      }
+    }
   }
   if (lane == 0) {
+    double* rw = red + wv * NR;
+    rw[0] = Mw;
+    rw[1] = swin;
+    rw[2] = s;
+    rw[3] = sw2;
 #pragma unroll
-    for (int v = 0; v < NV; ++v) red[wv * NV + v] = acc[v];
+    for (int j = 0; j < D; ++j) {
+      rw[4 + j] = a1[j];
+      rw[4 + D + j] = a2[j];
+    }
   }
   __syncthreads();
-  if (tid == 0) {
-    double tot[NV];
+  if (wv != 0) return;
+  // wave 0: lane v combines value v over the waves, in wave order
+  double M = red[0];
 #pragma unroll
-    for (int v = 0; v < NV; ++v) {
-      tot[v] = red[v];
-      for (int w = 1; w < NW; ++w) tot[v] += red[w * NV + v];
+  for (int w = 1; w < NW; ++w) M = fmax(M, red[w * NR]);
+  double tv = 0.0;
+  if (lane >= 1 && lane < NR) {
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+      const double mw = red[w * NR];
+      const double fw = (lane == 1) ? 1.0 : (mw == -INFINITY ? 0.0 : exp(mw - M));
+      tv += (lane == 3 ? fw * fw : fw) * red[w * NR + lane];
     }
-    const double S = tot[1], sw2 = tot[2], swin = tot[3];
-    pf_estimate_t* rec = f.hist + (f.t % f.hist_cap);
-    const double dlog = (M + log(S)) - log(swin);
-    const double ln = f.ctl->log_norm + dlog;
+  }
+  const double swin_t = readlane_d(tv, 1), S = readlane_d(tv, 2), sw2_t = readlane_d(tv, 3);
+  const int jl = lane < D ? lane : D - 1;
+  const double mx = __shfl(tv, 4 + jl, 64), mxx = __shfl(tv, 4 + D + jl, 64);
+  const double nx = wave_max(offv);
+  pf_estimate_t* rec = f.hist + (f.t % f.hist_cap);
+  if (lane < kMaxDim) {
+    double mean = 0.0, var = 0.0;
+    if (lane < D && lane < d) {
+      mean = mx / S;
+      var = fmax(mxx / S - mean * mean, 0.0);
+    }
+    rec->mean[lane] = mean;
+    rec->var[lane] = var;
+  }
+  if (lane == 0) {
+    const double ln = ln0 + ((M + log(S)) - log(swin_t));
     rec->t = f.t;
     rec->stage = f.k;
     rec->radix = f.radix;
     rec->valid = 1u;
     rec->log_normaliser = ln;
-    rec->ess = S * S / ((double)f.N * sw2);
+    rec->ess = S * S / ((double)f.N * sw2_t);
     rec->max_log_weight = M;
-    double nx = -INFINITY;
-    for (int sl = 0; sl < kOffSlots; ++sl) nx = fmax(nx, ord_decode(*off_slot(f.ctl, f.t + 1, sl)));
     rec->next_offset = nx;
-#pragma unroll
-    for (int j = 0; j < kMaxDim; ++j) {
-      double mean = 0.0, var = 0.0;
-      if (j < D && j < d) {
-        const int jj = j < D ? j : 0;
-        mean = tot[4 + jj] / S;
-        var = fmax(tot[4 + D + jj] / S - mean * mean, 0.0);
-      }
-      rec->mean[j] = mean;
-      rec->var[j] = var;
-    }
     f.ctl->log_norm = ln;
     f.ctl->t = f.t + 1;
   }
@@ -257,7 +305,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
 template <int D, typename T, int NT>
 __global__ void __launch_bounds__(NT) pf_finalize_kernel(FinArgs f, const T* part, uint32_t ntiles) {
   __shared__ double red[(NT / 64) * (4 + 2 * D)];
-  finalize_partials<D, T, NT>(f, part, ntiles, red);
+  finalize_partials<D, T, NT, fin_batch<D, T>()>(f, part, ntiles, red);
 }
 
 template <typename T, typename S> __device__ __forceinline__ FinArgs prev_fin_args(const StepArgs<T, S>& a) {
@@ -278,7 +326,7 @@ template <typename T, typename S> __device__ __forceinline__ FinArgs prev_fin_ar
 template <int D, typename T, typename S, int NT>
 __device__ void step_head_block(const StepArgs<T, S>& a, double* red) {
   clear_offset(a.ctl, a.t + 2, -INFINITY);
-  if (a.part_prev) finalize_partials<D, T, NT>(prev_fin_args(a), a.part_prev, a.ntiles_prev, red);
+  if (a.part_prev) finalize_partials<D, T, NT, 1>(prev_fin_args(a), a.part_prev, a.ntiles_prev, red);
 }
 
 // Partial sums of one tile from per-thread register values (relative to the

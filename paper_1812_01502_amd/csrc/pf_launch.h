@@ -144,7 +144,7 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       return hipGetLastError();
     }
     case LW_FINALIZE: {
-      hipLaunchKernelGGL((pf_finalize_kernel<D, T, 256>), dim3(1), dim3(256), 0, st, rq.fin,
+      hipLaunchKernelGGL((pf_finalize_kernel<D, T, 512>), dim3(1), dim3(512), 0, st, rq.fin,
                          reinterpret_cast<const T*>(rq.fin_part), rq.fin_ntiles);
       return hipGetLastError();
     }
