@@ -101,7 +101,7 @@ typedef struct {
   uint32_t reserved;
 } pf_config;
 
-/* Estimate of one completed step t (R9 of the design: the weighted cloud
+/* Estimate of one completed step t (the weighted cloud
  * before resampling, i.e. the filtering law of x_t given y_0..y_t). */
 typedef struct {
   uint32_t t;              /* step index the record belongs to */
