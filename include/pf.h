@@ -181,6 +181,22 @@ pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_
 pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, uint32_t t,
                        double log_norm);
 
+/* Checkpoint (host memory). pf_save writes the filter's complete state:
+ * a versioned header (configuration, model fingerprint, step counter,
+ * running log-normaliser, log-weight offset), the d state planes, the raw
+ * log-weights and the estimate record of the last step. With buf == NULL
+ * only *len_out (the size needed) is set. cap < size -> PF_E_INVALID.
+ * Synchronises. The blob is plain bytes, owned by the caller. */
+pf_status pf_save(pf_handle* h, void* buf, uint64_t cap, uint64_t* len_out);
+
+/* Restore a pf_save blob into a handle created with the same model, N,
+ * radix, resampler and dtype (seed and stream_id may differ: the
+ * continuation then draws other random numbers). Afterwards the handle
+ * continues exactly as the saved one would have: same states, weights,
+ * step counter and log-normaliser. Mismatch, truncation or corruption ->
+ * PF_E_INVALID with the handle unchanged. */
+pf_status pf_load(pf_handle* h, const void* buf, uint64_t len);
+
 /* Ancestor index a(i) (into the previous cloud) of every particle of the
  * last step (host output, N uint32; synchronises). Requires
  * cfg.keep_ancestors, else PF_E_STATE. */

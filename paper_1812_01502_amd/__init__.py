@@ -169,6 +169,18 @@ class Filter:
         self._check(self._lib.pf_set_state(self._h, x.ctypes.data_as(ctypes.c_void_p), wp,
                                            int(t), float(log_norm)))
 
+    def save(self) -> bytes:
+        """Checkpoint of the complete filter state (``pf_save``)."""
+        n = ctypes.c_uint64(0)
+        self._check(self._lib.pf_save(self._h, None, 0, ctypes.byref(n)))
+        buf = ctypes.create_string_buffer(n.value)
+        self._check(self._lib.pf_save(self._h, buf, n.value, ctypes.byref(n)))
+        return buf.raw
+
+    def load(self, blob: bytes):
+        """Restore a checkpoint made by ``save`` (``pf_load``)."""
+        self._check(self._lib.pf_load(self._h, blob, len(blob)))
+
     def ancestors(self) -> np.ndarray:
         a = np.empty(self.n, dtype=np.uint32)
         self._check(self._lib.pf_get_ancestors(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_uint32))))

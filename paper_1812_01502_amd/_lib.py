@@ -22,7 +22,7 @@ PF_DTYPE_F32, PF_DTYPE_BF16, PF_DTYPE_F64 = 0, 1, 2
 # Every symbol include/pf.h declares.
 EXPORTS = ("pf_create", "pf_destroy", "pf_reset", "pf_step", "pf_run", "pf_estimate",
            "pf_history", "pf_get_state", "pf_set_state", "pf_get_ancestors", "pf_info",
-           "pf_sync", "pf_status_string", "pf_last_error")
+           "pf_sync", "pf_status_string", "pf_last_error", "pf_save", "pf_load")
 
 DPTR = POINTER(c_double)
 
@@ -82,6 +82,8 @@ def load():
         "pf_get_ancestors": (c_int32, [H, POINTER(c_uint32)]),
         "pf_info": (c_int32, [H, POINTER(PfInfo)]),
         "pf_sync": (c_int32, [H]),
+        "pf_save": (c_int32, [H, c_void_p, c_uint64, POINTER(c_uint64)]),
+        "pf_load": (c_int32, [H, c_void_p, c_uint64]),
         "pf_status_string": (c_char_p, [c_int32]),
         "pf_last_error": (c_char_p, [H]),
     }

@@ -66,6 +66,7 @@ struct pf_handle {
   double* gscale = nullptr;
   uint32_t g_tile = 0, g_ntiles = 0, g_nt = 256, g_ppt = 1;
   uint64_t t = 0;
+  uint64_t model_hash = 0;   // FNV-1a of the model parameters (checkpoint check)
   bool lw_zero = true;       // every log-weight is 0 (global path bookkeeping)
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
@@ -108,6 +109,46 @@ bool finite_all(const double* p, size_t n) {
     if (!std::isfinite(p[i])) return false;
   return true;
 }
+
+// FNV-1a over the bytes of the model's parameters: a checkpoint may only be
+// loaded into a handle of the same model.
+uint64_t model_hash(const pf_model* m) {
+  uint64_t h = 1469598103934665603ull;
+  auto mix = [&](const void* p, size_t n) {
+    const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
+    for (size_t i = 0; i < n; ++i) {
+      h ^= b[i];
+      h *= 1099511628211ull;
+    }
+  };
+  mix(&m->kind, sizeof(m->kind));
+  mix(&m->d, sizeof(m->d));
+  const size_t dd = (size_t)m->d * m->d;
+  if (m->kind == PF_MODEL_LG) {
+    for (const double* a : {m->A, m->Q_chol, m->H, m->R_chol, m->P0_chol}) mix(a, dd * sizeof(double));
+    mix(m->m0, (size_t)m->d * sizeof(double));
+  } else {
+    mix(&m->phi, sizeof(double));
+    mix(&m->sigma, sizeof(double));
+    mix(&m->beta, sizeof(double));
+  }
+  return h;
+}
+
+// Checkpoint blob: this header, then the d state planes (storage type), the
+// raw log-weights (compute type) and the estimate record of the last step.
+struct BlobHeader {
+  char magic[8];
+  uint32_t version, header_bytes;
+  uint64_t n_particles, radix, model_hash, seed;
+  int32_t kind, d, resampler, dtype;
+  uint32_t stream_id, lw_zero;
+  uint64_t t;
+  double log_norm, offset;
+  uint64_t x_bytes, lw_bytes, rec_bytes;
+};
+constexpr char kBlobMagic[8] = {'P', 'F', 'B', 'F', 'L', 'Y', 'C', 'K'};
+constexpr uint32_t kBlobVersion = 1;
 
 // Inverse of a lower-triangular matrix (row-major d x d), FP64.
 void lower_inverse(const double* L, int d, double* out) {
@@ -587,6 +628,7 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   h->tsz = h->dtype == PF_DTYPE_F64 ? 8 : 4;
   h->ssz = h->dtype == PF_DTYPE_F64 ? 8 : (h->dtype == PF_DTYPE_BF16 ? 2 : 4);
   h->hist_cap = cfg->history ? cfg->history : 1;
+  h->model_hash = model_hash(model);
 
   auto bail = [&](pf_status s) {
     g_create_error = h->err;
@@ -822,6 +864,111 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "control upload");
   h->t = t;
+  return PF_OK;
+}
+
+pf_status pf_save(pf_handle* h, void* buf, uint64_t cap, uint64_t* len_out) {
+  if (!h || !len_out) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  const uint64_t xb = (uint64_t)h->d * h->N * h->ssz, lb = h->N * h->tsz, rb = sizeof(pf_estimate_t);
+  const uint64_t need = sizeof(BlobHeader) + xb + lb + rb;
+  *len_out = need;
+  if (!buf) return PF_OK;
+  if (cap < need) return fail(h, PF_E_INVALID, "checkpoint buffer too small");
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  Ctl c;
+  hipError_t e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "control copy");
+  BlobHeader hd;
+  std::memset(&hd, 0, sizeof(hd));
+  std::memcpy(hd.magic, kBlobMagic, 8);
+  hd.version = kBlobVersion;
+  hd.header_bytes = sizeof(BlobHeader);
+  hd.n_particles = h->N;
+  hd.radix = h->radix;
+  hd.model_hash = h->model_hash;
+  hd.seed = h->seed;
+  hd.kind = h->kind;
+  hd.d = h->d;
+  hd.resampler = h->resampler;
+  hd.dtype = h->dtype;
+  hd.stream_id = h->sid;
+  hd.lw_zero = h->lw_zero ? 1u : 0u;
+  hd.t = h->t;
+  hd.log_norm = c.log_norm;
+  double off = -INFINITY;
+  for (int sl = 0; sl < kOffSlots; ++sl)
+    off = std::max(off, ord_decode(c.offs[(h->t % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
+  hd.offset = off;
+  hd.x_bytes = xb;
+  hd.lw_bytes = lb;
+  hd.rec_bytes = rb;
+  char* out = reinterpret_cast<char*>(buf);
+  std::memcpy(out, &hd, sizeof(hd));
+  out += sizeof(hd);
+  e = hipMemcpy(out, h->x[h->cur], xb, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "state copy");
+  out += xb;
+  if (h->lw_zero) {
+    std::memset(out, 0, lb);
+  } else {
+    e = hipMemcpy(out, h->lw[h->cur], lb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "log-weight copy");
+  }
+  out += lb;
+  if (h->t > 0) {
+    e = hipMemcpy(out, h->hist + (h->t - 1) % h->hist_cap, rb, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "record copy");
+  } else {
+    std::memset(out, 0, rb);
+  }
+  return PF_OK;
+}
+
+pf_status pf_load(pf_handle* h, const void* buf, uint64_t len) {
+  if (!h || !buf) return PF_E_INVALID;
+  if (poisoned(h)) return PF_E_STATE;
+  BlobHeader hd;
+  if (len < sizeof(hd)) return fail(h, PF_E_INVALID, "checkpoint shorter than its header");
+  std::memcpy(&hd, buf, sizeof(hd));
+  if (std::memcmp(hd.magic, kBlobMagic, 8) != 0 || hd.version != kBlobVersion ||
+      hd.header_bytes != sizeof(BlobHeader))
+    return fail(h, PF_E_INVALID, "not a checkpoint of this library version");
+  const uint64_t xb = (uint64_t)h->d * h->N * h->ssz, lb = h->N * h->tsz, rb = sizeof(pf_estimate_t);
+  if (hd.n_particles != h->N || hd.radix != h->radix || hd.model_hash != h->model_hash ||
+      hd.kind != h->kind || hd.d != h->d || hd.resampler != h->resampler || hd.dtype != h->dtype ||
+      hd.x_bytes != xb || hd.lw_bytes != lb || hd.rec_bytes != rb)
+    return fail(h, PF_E_INVALID, "checkpoint of a different model or configuration");
+  if (len < sizeof(hd) + xb + lb + rb) return fail(h, PF_E_INVALID, "checkpoint truncated");
+  if (hd.t > 0xFFFFFFFFull || !std::isfinite(hd.log_norm) || !std::isfinite(hd.offset))
+    return fail(h, PF_E_INVALID, "checkpoint header corrupt");
+  pf_status s = pf_sync(h);
+  if (s != PF_OK) return s;
+  const char* in = reinterpret_cast<const char*>(buf) + sizeof(hd);
+  hipError_t e = hipMemcpy(h->x[h->cur], in, xb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "state upload");
+  in += xb;
+  e = hipMemcpy(h->lw[h->cur], in, lb, hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "log-weight upload");
+  in += lb;
+  h->lw_zero = hd.lw_zero != 0;
+  h->t = hd.t;
+  h->fin_pending = false;
+  Ctl c;
+  e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "control copy");
+  c.log_norm = hd.log_norm;
+  c.t = (uint32_t)hd.t;
+  for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
+  // the raw log-weights come back with the offset the next step subtracts
+  c.offs[(hd.t % kOffRing) * kOffSlots * kOffStride] = ord_encode(hd.offset);
+  e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
+  if (e != hipSuccess) return hip_fail(h, e, "control upload");
+  if (hd.t > 0) {
+    e = hipMemcpy(h->hist + (hd.t - 1) % h->hist_cap, in, rb, hipMemcpyHostToDevice);
+    if (e != hipSuccess) return hip_fail(h, e, "record upload");
+  }
   return PF_OK;
 }
 

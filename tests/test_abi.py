@@ -162,3 +162,6 @@ def test_misc_entry_points_without_device(lib):
     assert lib.pf_status_string(-5) == b"non-finite value"
     assert lib.pf_step(None, None) == -1
     assert lib.pf_sync(None) == -1
+    n = ctypes.c_uint64(0)
+    assert lib.pf_save(None, None, 0, ctypes.byref(n)) == -1
+    assert lib.pf_load(None, None, 0) == -1
