@@ -208,6 +208,88 @@ pf_status pf_info(pf_handle* h, pf_info_t* out);
 /* Wait for all work of the handle (hipStreamSynchronize). */
 pf_status pf_sync(pf_handle* h);
 
+/* ------------------------------------------------------------------------
+ * Batched filters: n independent filters (each its own model, N, radix,
+ * resampler, seed and stream_id) advanced together. Every filter computes
+ * exactly what a single pf_handle with the same configuration computes
+ * (same states and log-weights bit for bit; estimates up to the summation
+ * order of the reductions). Filters are grouped by (state dimension, model
+ * kind); one step is one kernel launch per group plus one reduction launch
+ * per group, with no host data besides two device pointers, so pf_batch_run
+ * can capture many steps in one HIP graph.
+ * Restrictions: FP32 states, 512 <= N <= 2^30, stage radices <= 64 (no
+ * global path), no ancestor recording.
+ * ------------------------------------------------------------------------ */
+typedef struct pf_batch pf_batch;
+
+/* One autotuner trial: a (pairs per thread, radix) candidate of a class,
+ * the measured time of one batched step, and whether it was chosen. */
+typedef struct {
+  uint32_t class_index;
+  uint32_t dim;             /* compiled state dimension of the class */
+  uint32_t model_kind;      /* 0 dense LG, 1 LG with diagonal noise, 2 SV */
+  uint32_t pairs_per_thread;/* tile of 512 x pairs_per_thread particles */
+  uint32_t radix;
+  uint32_t chosen;
+  float ms_per_step;
+  uint32_t reserved;
+} pf_batch_tune_t;
+
+/* Create n filters from models[i] and cfgs[i] (host arrays, copied) and run
+ * every initialisation (Algorithm 1). cfgs[i].radix = 0 asks the autotuner
+ * to choose the radix of that filter: per class it times one batched step
+ * for each tile size and radix in {2, ..., 64} and keeps, at the fastest
+ * tile size, the largest radix within 10 % of the fastest time (see
+ * pf_batch_tuning). cfgs[i].history and the dtype other than F32 are not
+ * supported (history is 1). Errors as pf_create; the message of a failed
+ * create is pf_batch_last_error(NULL). */
+pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_t n,
+                          void* hip_stream, pf_batch** out);
+
+/* Release every device buffer. NULL is accepted. */
+pf_status pf_batch_destroy(pf_batch* b);
+
+/* One time step of every active filter. y_dev (device, float): the packed
+ * observations, filter i's d_i values at offset sum_{j<i} d_j. active_dev
+ * (device, n bytes, or NULL for all): filters with 0 do not step (their
+ * state, counter and record are untouched). Asynchronous. */
+pf_status pf_batch_step(pf_batch* b, const float* y_dev, const uint8_t* active_dev);
+
+/* n_steps batched steps, step j reading y_dev + j * y_stride (y_stride >=
+ * sum d_i), the same active mask for all; with use_graph != 0 captured in
+ * one HIP graph and replayed once. Asynchronous. */
+pf_status pf_batch_run(pf_batch* b, const float* y_dev, uint32_t n_steps, uint64_t y_stride,
+                       const uint8_t* active_dev, int32_t use_graph);
+
+/* Estimate record of the last step of every filter (host output, n
+ * records; a filter that has not stepped has valid = 0). Synchronises. */
+pf_status pf_batch_estimates(pf_batch* b, pf_estimate_t* out);
+
+/* Plan of filter f (radices, tile size, completed steps). */
+pf_status pf_batch_filter_info(pf_batch* b, uint32_t f, pf_info_t* out);
+
+/* Autotuner trials (host output, up to n_max; out may be NULL to count). */
+pf_status pf_batch_tuning(pf_batch* b, pf_batch_tune_t* out, uint32_t n_max, uint32_t* n_out);
+
+/* State of filter f (host, layouts as pf_get_state with float storage). */
+pf_status pf_batch_get_state(pf_batch* b, uint32_t f, float* x_host, float* logw_host,
+                             uint32_t* t_out, double* log_norm);
+
+/* Overwrite the state of filter f (as pf_set_state). */
+pf_status pf_batch_set_state(pf_batch* b, uint32_t f, const float* x_host, const float* logw_host,
+                             uint32_t t, double log_norm);
+
+/* Re-initialise filter f with a new seed and stream_id (t = 0), e.g. to
+ * give its slot to a new stream. Synchronises. */
+pf_status pf_batch_reset(pf_batch* b, uint32_t f, uint64_t seed, uint32_t stream_id);
+
+/* Wait for all work of the batch. */
+pf_status pf_batch_sync(pf_batch* b);
+
+/* Last error message of the batch ("" if none); NULL: the last failed
+ * pf_batch_create of this thread. */
+const char* pf_batch_last_error(const pf_batch* b);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

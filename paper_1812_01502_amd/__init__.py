@@ -18,7 +18,7 @@ import numpy as np
 
 from . import _lib as L
 
-__all__ = ["Filter", "PfError", "load_library", "DTYPES", "RESAMPLERS"]
+__all__ = ["Filter", "BatchFilter", "PfError", "load_library", "DTYPES", "RESAMPLERS"]
 
 DTYPES = {"f32": L.PF_DTYPE_F32, "bf16": L.PF_DTYPE_BF16, "f64": L.PF_DTYPE_F64}
 RESAMPLERS = {"multinomial": L.PF_RESAMPLE_MULTINOMIAL, "systematic": L.PF_RESAMPLE_SYSTEMATIC}
@@ -38,6 +38,27 @@ def _dptr(a):
     return a.ctypes.data_as(L.DPTR)
 
 
+def _pf_model(model, keep: list) -> L.PfModel:
+    """``pf_model`` from a model object (arrays kept alive in ``keep``)."""
+    m = L.PfModel()
+    m.d = int(model.d)
+    if model.kind == "lg":
+        m.kind = L.PF_MODEL_LG
+        for nm in ("A", "Q_chol", "H", "R_chol", "P0_chol"):
+            arr = np.ascontiguousarray(np.asarray(getattr(model, nm), dtype=np.float64))
+            keep.append(arr)
+            setattr(m, nm, _dptr(arr))
+        m0 = np.ascontiguousarray(np.asarray(model.m0, dtype=np.float64))
+        keep.append(m0)
+        m.m0 = _dptr(m0)
+    elif model.kind == "sv":
+        m.kind = L.PF_MODEL_SV
+        m.phi, m.sigma, m.beta = float(model.phi), float(model.sigma), float(model.beta)
+    else:
+        raise ValueError(f"unknown model kind {model.kind!r}")
+    return m
+
+
 class Filter:
     """One particle filter on the GPU.
 
@@ -54,22 +75,7 @@ class Filter:
         self.n = int(n)
         self.dtype = dtype
         self._keep = []
-        m = L.PfModel()
-        m.d = self.d
-        if model.kind == "lg":
-            m.kind = L.PF_MODEL_LG
-            for nm in ("A", "Q_chol", "H", "R_chol", "P0_chol"):
-                arr = np.ascontiguousarray(np.asarray(getattr(model, nm), dtype=np.float64))
-                self._keep.append(arr)
-                setattr(m, nm, _dptr(arr))
-            m0 = np.ascontiguousarray(np.asarray(model.m0, dtype=np.float64))
-            self._keep.append(m0)
-            m.m0 = _dptr(m0)
-        elif model.kind == "sv":
-            m.kind = L.PF_MODEL_SV
-            m.phi, m.sigma, m.beta = float(model.phi), float(model.sigma), float(model.beta)
-        else:
-            raise ValueError(f"unknown model kind {model.kind!r}")
+        m = _pf_model(model, self._keep)
         c = L.PfConfig()
         c.n_particles = self.n
         c.radix = int(radix)
@@ -205,3 +211,114 @@ def f32_to_bf16(x: np.ndarray) -> np.ndarray:
     u = np.asarray(x, dtype=np.float32).view(np.uint32).astype(np.uint64)
     u = u + 0x7FFF + ((u >> 16) & 1)
     return (u >> 16).astype(np.uint16)
+
+
+class BatchFilter:
+    """Many independent filters advanced together (``pf_batch_*``).
+
+    ``models``, ``ns``, ``radices`` (0 = autotune), ``seeds`` and
+    ``stream_ids`` are per-filter sequences. Observations of one step are
+    packed in filter order (filter i's ``d_i`` values at ``y_offsets[i]``).
+    """
+
+    def __init__(self, models, ns, radices, seeds, stream_ids=None, resampler: str = "multinomial",
+                 stream: int | None = None):
+        self._lib = L.load()
+        n = len(models)
+        self.n = n
+        self.ds = [int(m.d) for m in models]
+        self.ns = [int(v) for v in ns]
+        self.y_offsets = np.concatenate([[0], np.cumsum(self.ds)[:-1]]).astype(np.int64)
+        self.y_len = int(sum(self.ds))
+        keep = []
+        M = (L.PfModel * n)()
+        C = (L.PfConfig * n)()
+        sids = stream_ids if stream_ids is not None else range(n)
+        for i, (m, N, r, sd, sid) in enumerate(zip(models, ns, radices, seeds, sids)):
+            M[i] = _pf_model(m, keep)
+            C[i].n_particles = int(N)
+            C[i].radix = int(r)
+            C[i].resampler = RESAMPLERS[resampler]
+            C[i].state_dtype = L.PF_DTYPE_F32
+            C[i].seed = int(sd)
+            C[i].stream_id = int(sid)
+            C[i].history = 1
+        h = ctypes.c_void_p()
+        st = self._lib.pf_batch_create(M, C, n, ctypes.c_void_p(stream) if stream else None,
+                                       ctypes.byref(h))
+        if st != L.PF_OK:
+            raise PfError(st, self._lib.pf_batch_last_error(None).decode())
+        self._h = h
+
+    def _check(self, st):
+        if st != L.PF_OK:
+            raise PfError(st, self._lib.pf_batch_last_error(self._h).decode())
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._lib.pf_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def step(self, y_dev_ptr: int, active_dev_ptr: int | None = None):
+        self._check(self._lib.pf_batch_step(self._h, ctypes.c_void_p(int(y_dev_ptr)),
+                                            ctypes.c_void_p(int(active_dev_ptr)) if active_dev_ptr else None))
+
+    def run(self, y_dev_ptr: int, n_steps: int, stride: int | None = None,
+            active_dev_ptr: int | None = None, use_graph: bool = False):
+        self._check(self._lib.pf_batch_run(
+            self._h, ctypes.c_void_p(int(y_dev_ptr)), int(n_steps),
+            int(stride if stride is not None else self.y_len),
+            ctypes.c_void_p(int(active_dev_ptr)) if active_dev_ptr else None, 1 if use_graph else 0))
+
+    def sync(self):
+        self._check(self._lib.pf_batch_sync(self._h))
+
+    def estimates(self) -> list:
+        recs = (L.PfEstimate * self.n)()
+        self._check(self._lib.pf_batch_estimates(self._h, recs))
+        return [Filter._rec(recs[i], self.ds[i]) for i in range(self.n)]
+
+    def info(self, f: int) -> dict:
+        i = L.PfInfo()
+        self._check(self._lib.pf_batch_filter_info(self._h, int(f), ctypes.byref(i)))
+        return dict(n=i.n_particles, d=i.d, stages=list(i.radices[:i.n_stages]),
+                    tile=i.tile_elems[0], t=i.t, device_bytes=i.device_bytes)
+
+    def tuning(self) -> list:
+        cnt = ctypes.c_uint32()
+        self._check(self._lib.pf_batch_tuning(self._h, None, 0, ctypes.byref(cnt)))
+        arr = (L.PfBatchTune * max(cnt.value, 1))()
+        self._check(self._lib.pf_batch_tuning(self._h, arr, cnt.value, ctypes.byref(cnt)))
+        return [dict(cls=a.class_index, dim=a.dim, model_kind=a.model_kind, ppt=a.pairs_per_thread,
+                     radix=a.radix, chosen=bool(a.chosen), ms=a.ms_per_step) for a in arr[:cnt.value]]
+
+    def get_state(self, f: int):
+        d, N = self.ds[f], self.ns[f]
+        x = np.empty((d, N), dtype=np.float32)
+        w = np.empty(N, dtype=np.float32)
+        t = ctypes.c_uint32()
+        ln = ctypes.c_double()
+        self._check(self._lib.pf_batch_get_state(self._h, int(f), x.ctypes.data_as(ctypes.c_void_p),
+                                                 w.ctypes.data_as(ctypes.c_void_p), ctypes.byref(t),
+                                                 ctypes.byref(ln)))
+        return x, w, t.value, ln.value
+
+    def set_state(self, f: int, x, logw=None, t: int = 0, log_norm: float = 0.0):
+        d, N = self.ds[f], self.ns[f]
+        x = np.ascontiguousarray(np.asarray(x, dtype=np.float32).reshape(d, N))
+        wp = None
+        if logw is not None:
+            w = np.ascontiguousarray(np.asarray(logw, dtype=np.float32).reshape(N))
+            wp = w.ctypes.data_as(ctypes.c_void_p)
+        self._check(self._lib.pf_batch_set_state(self._h, int(f), x.ctypes.data_as(ctypes.c_void_p), wp,
+                                                 int(t), float(log_norm)))
+
+    def reset(self, f: int, seed: int, stream_id: int):
+        self._check(self._lib.pf_batch_reset(self._h, int(f), int(seed), int(stream_id)))
+

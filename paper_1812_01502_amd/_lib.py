@@ -22,7 +22,10 @@ PF_DTYPE_F32, PF_DTYPE_BF16, PF_DTYPE_F64 = 0, 1, 2
 # Every symbol include/pf.h declares.
 EXPORTS = ("pf_create", "pf_destroy", "pf_reset", "pf_step", "pf_run", "pf_estimate",
            "pf_history", "pf_get_state", "pf_set_state", "pf_get_ancestors", "pf_info",
-           "pf_sync", "pf_status_string", "pf_last_error", "pf_save", "pf_load")
+           "pf_sync", "pf_status_string", "pf_last_error", "pf_save", "pf_load",
+           "pf_batch_create", "pf_batch_destroy", "pf_batch_step", "pf_batch_run",
+           "pf_batch_estimates", "pf_batch_filter_info", "pf_batch_tuning", "pf_batch_get_state",
+           "pf_batch_set_state", "pf_batch_reset", "pf_batch_sync", "pf_batch_last_error")
 
 DPTR = POINTER(c_double)
 
@@ -50,6 +53,12 @@ class PfInfo(ctypes.Structure):
     _fields_ = [("n_particles", c_uint64), ("d", c_uint32), ("n_stages", c_uint32),
                 ("radices", c_uint32 * 32), ("global_path", c_uint32), ("state_dtype", c_uint32),
                 ("device_bytes", c_uint64), ("t", c_uint32), ("tile_elems", c_uint32 * 32)]
+
+
+class PfBatchTune(ctypes.Structure):
+    _fields_ = [("class_index", c_uint32), ("dim", c_uint32), ("model_kind", c_uint32),
+                ("pairs_per_thread", c_uint32), ("radix", c_uint32), ("chosen", c_uint32),
+                ("ms_per_step", ctypes.c_float), ("reserved", c_uint32)]
 
 
 _lib = None
@@ -84,6 +93,19 @@ def load():
         "pf_sync": (c_int32, [H]),
         "pf_save": (c_int32, [H, c_void_p, c_uint64, POINTER(c_uint64)]),
         "pf_load": (c_int32, [H, c_void_p, c_uint64]),
+        "pf_batch_create": (c_int32, [POINTER(PfModel), POINTER(PfConfig), c_uint32, c_void_p,
+                                      POINTER(H)]),
+        "pf_batch_destroy": (c_int32, [H]),
+        "pf_batch_step": (c_int32, [H, c_void_p, c_void_p]),
+        "pf_batch_run": (c_int32, [H, c_void_p, c_uint32, c_uint64, c_void_p, c_int32]),
+        "pf_batch_estimates": (c_int32, [H, POINTER(PfEstimate)]),
+        "pf_batch_filter_info": (c_int32, [H, c_uint32, POINTER(PfInfo)]),
+        "pf_batch_tuning": (c_int32, [H, POINTER(PfBatchTune), c_uint32, POINTER(c_uint32)]),
+        "pf_batch_get_state": (c_int32, [H, c_uint32, c_void_p, c_void_p, POINTER(c_uint32), DPTR]),
+        "pf_batch_set_state": (c_int32, [H, c_uint32, c_void_p, c_void_p, c_uint32, c_double]),
+        "pf_batch_reset": (c_int32, [H, c_uint32, c_uint64, c_uint32]),
+        "pf_batch_sync": (c_int32, [H]),
+        "pf_batch_last_error": (c_char_p, [H]),
         "pf_status_string": (c_char_p, [c_int32]),
         "pf_last_error": (c_char_p, [H]),
     }

@@ -541,16 +541,12 @@ __device__ __forceinline__ double seg_scan(double v, uint32_t lr, uint32_t q) {
 }
 
 // ---------------------------------------------------------------------------
-// Fused butterfly step (radix r < N). Block 0 is the head block; block
-// b >= 1 processes a tile of r x C particles.
+// Fused butterfly step (radix r < N) on one tile of r x C particles: the
+// body shared by the single-filter kernel and the batched kernel.
 // ---------------------------------------------------------------------------
 template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
-__global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
-  extern __shared__ __align__(16) unsigned char smem[];
-  if (blockIdx.x == 0) {
-    step_head_block<D, T, S, NT>(a, reinterpret_cast<double*>(smem));
-    return;
-  }
+__device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const uint32_t tile,
+                                               unsigned char* smem) {
   constexpr int NLOC = 2 * PPT;
   constexpr int PS = partial_stride(D);
   const int d = (int)a.d;
@@ -576,7 +572,6 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   T* coltot = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
   T* colu0 = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
 
-  const uint32_t tile = xcd_tile(blockIdx.x - 1u, a.ntiles);
   const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
   const uint64_t N = a.N;
   const T off = (T)read_offset(a.ctl, a.t);
@@ -784,6 +779,120 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
       a.anc[g0] = ai[0];
       a.anc[g0 + 1] = ai[1];
     }
+  }
+}
+
+// Single filter: block 0 is the head block (reduction of the previous
+// step); block b >= 1 processes tile xcd_tile(b - 1).
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
+__global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  if (blockIdx.x == 0) {
+    step_head_block<D, T, S, NT>(a, reinterpret_cast<double*>(smem));
+    return;
+  }
+  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH>(a, xcd_tile(blockIdx.x - 1u, a.ntiles), smem);
+}
+
+// ---------------------------------------------------------------------------
+// Batched filters: many independent filters (each with its own model, N,
+// radix, seed and step counter) advanced by one launch per (dimension,
+// model kind) class. Each block takes one tile of one filter; a filter's
+// stage comes from its own step counter, so the launches need no per-step
+// host data beyond the observation pointer and can be replayed from a graph.
+// ---------------------------------------------------------------------------
+struct BatchStage {   // stage k of one filter
+  uint32_t log2r, log2R, log2C, pad;
+  float lnr;
+  uint32_t reserved[3];
+};
+
+struct BatchFilter {  // one filter of the batch (device table entry)
+  float* x[2];        // state planes [d][N], by step parity
+  float* lw[2];       // log-weights [N], by step parity
+  const ModelParams<float>* mp;
+  float* part;        // tile partial records of the current step
+  Ctl* ctl;
+  pf_estimate_t* rec; // estimate record of the last step
+  uint64_t N;
+  uint32_t d, S, stage0, ntiles;
+  uint32_t first_block, yoff, sid, k0;
+  uint32_t k1, systematic, reserved[2];
+};
+
+struct BatchArgs {
+  const BatchFilter* filt;
+  const BatchStage* stages;
+  const uint32_t* block_filter;   // step kernel: block -> filter
+  const uint32_t* class_filters;  // finalize kernel: block -> filter
+  const uint8_t* active;          // NULL: every filter steps
+  const float* y;                 // packed observations of this step
+  uint32_t* tcur;                 // completed steps per filter
+};
+
+template <int D, int MK, int NT, int PPT>
+__global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t f = ba.block_filter[blockIdx.x];
+  if (ba.active && !ba.active[f]) return;
+  const BatchFilter& F = ba.filt[f];
+  const uint32_t t = ba.tcur[f];
+  const uint32_t k = t % F.S;
+  const BatchStage& sg = ba.stages[F.stage0 + k];
+  StepArgs<float, float> a;
+  a.x_in = F.x[t & 1u];
+  a.x_out = F.x[(t + 1u) & 1u];
+  a.lw_in = F.lw[t & 1u];
+  a.lw_out = F.lw[(t + 1u) & 1u];
+  a.anc = nullptr;
+  a.y_dev = ba.y + F.yoff;
+  a.mp = F.mp;
+  a.part_out = F.part;
+  a.part_prev = nullptr;
+  a.ctl = F.ctl;
+  a.hist = F.rec;
+  a.hist_cap = 1u;
+  a.d = F.d;
+  a.N = F.N;
+  a.log2r = sg.log2r;
+  a.log2R = sg.log2R;
+  a.log2C = sg.log2C;
+  a.pad = sg.pad;
+  a.t = t;
+  a.k = k;
+  a.ntiles = F.ntiles;
+  a.radix = 1u << sg.log2r;
+  a.sid = F.sid;
+  a.k0 = F.k0;
+  a.k1 = F.k1;
+  a.systematic = F.systematic;
+  a.lnr = sg.lnr;
+  step_tile_body<D, MK, float, float, NT, PPT, false>(a, blockIdx.x - F.first_block, smem);
+}
+
+// Reduction of one filter's tile partials per block (after the class's
+// step kernel): estimate record, log-normaliser, offset ring, step counter.
+template <int D, int NT>
+__global__ void __launch_bounds__(NT) pf_batch_finalize(BatchArgs ba) {
+  __shared__ double red[(NT / 64) * (4 + 2 * D)];
+  const uint32_t f = ba.class_filters[blockIdx.x];
+  if (ba.active && !ba.active[f]) return;
+  const BatchFilter& F = ba.filt[f];
+  const uint32_t t = ba.tcur[f];
+  const uint32_t k = t % F.S;
+  FinArgs fa;
+  fa.ctl = F.ctl;
+  fa.hist = F.rec;
+  fa.hist_cap = 1u;
+  fa.t = t;
+  fa.k = k;
+  fa.radix = 1u << ba.stages[F.stage0 + k].log2r;
+  fa.d = F.d;
+  fa.N = F.N;
+  finalize_partials<D, float, NT, fin_batch<D, float>()>(fa, F.part, F.ntiles, red);
+  if (threadIdx.x < 64u) {
+    clear_offset(F.ctl, t + 2u, -INFINITY);
+    if (threadIdx.x == 0) ba.tcur[f] = t + 1u;
   }
 }
 

@@ -181,6 +181,45 @@ static hipError_t launch_any(const LaunchReq& rq, const void* args, hipStream_t 
   return hipErrorInvalidValue;
 }
 
+// Batched filters (FP32): the step kernel of one (D, model kind, PPT) class
+// or its finalize kernel.
+struct BatchReq {
+  int finalize;  // 0: step tiles, 1: reductions
+  int D, mk, ppt;
+  uint32_t grid;
+  size_t lds;
+};
+constexpr int kBatchNT = 256;
+// Pairs per thread of the batched tiles (E = 512 PPT particles per tile).
+constexpr bool batch_ppt_ok(int D, int ppt) { return ppt == 1 || (ppt == 2 && D <= 8); }
+
+template <int D, int MK>
+static hipError_t launch_batch_model(const BatchReq& rq, const BatchArgs& a, hipStream_t st) {
+  if (rq.finalize) {
+    hipLaunchKernelGGL((pf_batch_finalize<D, kBatchNT>), dim3(rq.grid), dim3(kBatchNT), 0, st, a);
+    return hipGetLastError();
+  }
+  if (rq.ppt == 1) {
+    auto k = pf_batch_tile<D, MK, kBatchNT, 1>;
+    hipError_t e = ensure_lds(k, rq.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kBatchNT), rq.lds, st, a);
+    return hipGetLastError();
+  }
+  if constexpr (D <= 8) {
+    if (rq.ppt == 2) {
+      auto k = pf_batch_tile<D, MK, kBatchNT, 2>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kBatchNT), rq.lds, st, a);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch(const BatchReq& rq, const BatchArgs& a, hipStream_t st);
+
 // Entry points of the three dtype translation units.
 hipError_t launch_f32(const LaunchReq& rq, const void* args, hipStream_t st);
 hipError_t launch_bf16(const LaunchReq& rq, const void* args, hipStream_t st);

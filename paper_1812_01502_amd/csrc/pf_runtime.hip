@@ -10,30 +10,14 @@
 #include <vector>
 
 #include "../../include/pf.h"
-#include "pf_launch.h"
+#include "pf_host.h"
 
 using namespace pfk;
+using namespace pfh;
 
 namespace {
 
 thread_local std::string g_create_error;
-
-struct StagePlan {
-  uint32_t r, log2r;
-  uint64_t R;
-  uint32_t log2R;
-  // tile kernel geometry
-  int blockpath, nt, ppt;
-  uint32_t C, log2C, pad, ntiles;
-  size_t lds;
-};
-
-bool is_pow2(uint64_t v) { return v && !(v & (v - 1)); }
-uint32_t ilog2(uint64_t v) {
-  uint32_t l = 0;
-  while ((1ull << l) < v) ++l;
-  return l;
-}
 
 }  // namespace
 
@@ -104,37 +88,6 @@ pf_status dalloc(pf_handle* h, void** p, size_t bytes) {
   return PF_OK;
 }
 
-bool finite_all(const double* p, size_t n) {
-  for (size_t i = 0; i < n; ++i)
-    if (!std::isfinite(p[i])) return false;
-  return true;
-}
-
-// FNV-1a over the bytes of the model's parameters: a checkpoint may only be
-// loaded into a handle of the same model.
-uint64_t model_hash(const pf_model* m) {
-  uint64_t h = 1469598103934665603ull;
-  auto mix = [&](const void* p, size_t n) {
-    const unsigned char* b = reinterpret_cast<const unsigned char*>(p);
-    for (size_t i = 0; i < n; ++i) {
-      h ^= b[i];
-      h *= 1099511628211ull;
-    }
-  };
-  mix(&m->kind, sizeof(m->kind));
-  mix(&m->d, sizeof(m->d));
-  const size_t dd = (size_t)m->d * m->d;
-  if (m->kind == PF_MODEL_LG) {
-    for (const double* a : {m->A, m->Q_chol, m->H, m->R_chol, m->P0_chol}) mix(a, dd * sizeof(double));
-    mix(m->m0, (size_t)m->d * sizeof(double));
-  } else {
-    mix(&m->phi, sizeof(double));
-    mix(&m->sigma, sizeof(double));
-    mix(&m->beta, sizeof(double));
-  }
-  return h;
-}
-
 // Checkpoint blob: this header, then the d state planes (storage type), the
 // raw log-weights (compute type) and the estimate record of the last step.
 struct BlobHeader {
@@ -150,135 +103,12 @@ struct BlobHeader {
 constexpr char kBlobMagic[8] = {'P', 'F', 'B', 'F', 'L', 'Y', 'C', 'K'};
 constexpr uint32_t kBlobVersion = 1;
 
-// Inverse of a lower-triangular matrix (row-major d x d), FP64.
-void lower_inverse(const double* L, int d, double* out) {
-  for (int i = 0; i < d * d; ++i) out[i] = 0.0;
-  for (int j = 0; j < d; ++j) {
-    out[j * d + j] = 1.0 / L[j * d + j];
-    for (int i = j + 1; i < d; ++i) {
-      double s = 0.0;
-      for (int k = j; k < i; ++k) s += L[i * d + k] * out[k * d + j];
-      out[i * d + j] = -s / L[i * d + i];
-    }
-  }
-}
-
-template <typename T>
-void fill_params(const pf_model* m, int d, ModelParams<T>* P, int* mk_out) {
-  std::memset(P, 0, sizeof(*P));
-  if (m->kind == PF_MODEL_SV) {
-    P->phi = (T)m->phi;
-    P->sigma = (T)m->sigma;
-    P->inv2b2 = (T)(1.0 / (2.0 * m->beta * m->beta));
-    P->sd0 = (T)(m->sigma / std::sqrt(1.0 - m->phi * m->phi));
-    P->lconst = (T)(-0.5 * std::log(2.0 * M_PI * m->beta * m->beta));
-    *mk_out = MK_SV;
-    return;
-  }
-  std::vector<double> Li(d * d);
-  lower_inverse(m->R_chol, d, Li.data());
-  double logdet = 0.0;
-  for (int j = 0; j < d; ++j) logdet += std::log(m->R_chol[j * d + j]);
-  P->lconst = (T)(-logdet - 0.5 * d * std::log(2.0 * M_PI));
-  bool diag = true;
-  for (int i = 0; i < d; ++i)
-    for (int j = 0; j < d; ++j) {
-      const double hij = m->H[i * d + j];
-      if (hij != (i == j ? 1.0 : 0.0)) diag = false;
-      if (i != j && (m->R_chol[i * d + j] != 0.0 || m->Q_chol[i * d + j] != 0.0)) diag = false;
-    }
-  for (int i = 0; i < d; ++i) {
-    P->m0[i] = (T)m->m0[i];
-    P->qd[i] = (T)m->Q_chol[i * d + i];
-    P->lid[i] = (T)Li[i * d + i];
-    for (int j = 0; j < d; ++j) {
-      P->A[i * kMaxDim + j] = (T)m->A[i * d + j];
-      P->H[i * kMaxDim + j] = (T)m->H[i * d + j];
-      if (j <= i) {
-        P->Lq[i * kMaxDim + j] = (T)m->Q_chol[i * d + j];
-        P->Li[i * kMaxDim + j] = (T)Li[i * d + j];
-        P->L0[i * kMaxDim + j] = (T)m->P0_chol[i * d + j];
-      }
-    }
-  }
-  *mk_out = diag ? MK_LG_DIAG : MK_LG_DENSE;
-}
-
 hipError_t launch(pf_handle* h, const LaunchReq& rq, const void* args) {
   switch (h->dtype) {
     case PF_DTYPE_F32: return launch_f32(rq, args, h->stream);
     case PF_DTYPE_BF16: return launch_bf16(rq, args, h->stream);
     default: return launch_f64(rq, args, h->stream);
   }
-}
-
-// Bank-conflict cost of the LDS pad for the per-group scalar arrays
-// (layout [column][r + pad]): phase-A/C accesses by consecutive pairs and
-// phase-B accesses by group lanes, evaluated for 32 and 64 banks.
-uint32_t choose_pad(uint32_t r, uint32_t C, uint32_t log2R, int nt) {
-  const uint32_t log2r = ilog2(r), log2C = ilog2(C);
-  const bool wide = log2R >= log2C;
-  auto coords = [&](uint32_t f, uint32_t& q, uint32_t& c) {
-    if (wide) {
-      q = f >> log2C;
-      c = f & (C - 1);
-    } else {
-      const uint32_t sh = log2r + log2R;
-      const uint32_t hb = f >> sh, rem = f & ((1u << sh) - 1);
-      q = rem >> log2R;
-      c = (hb << log2R) | (rem & ((1u << log2R) - 1));
-    }
-  };
-  uint32_t best = 0;
-  double best_cost = 1e30;
-  const uint32_t cands[] = {0, 1, 2, 3, 4, 5, 8};
-  for (uint32_t pad : cands) {
-    const uint32_t P = r + pad;
-    double cost = 0;
-    for (int banks : {32, 64}) {
-      auto degree = [&](const std::vector<uint32_t>& addr, int lanes_per_cycle) {
-        double tot = 0;
-        for (size_t g = 0; g < addr.size(); g += lanes_per_cycle) {
-          std::vector<std::vector<uint32_t>> b(banks);
-          int mx = 0;
-          for (size_t i = g; i < g + lanes_per_cycle && i < addr.size(); ++i) {
-            auto& v = b[addr[i] % banks];
-            bool seen = false;
-            for (uint32_t a : v) seen |= (a == addr[i]);
-            if (!seen) v.push_back(addr[i]);
-            mx = std::max<int>(mx, (int)v.size());
-          }
-          tot += mx;
-        }
-        return tot;
-      };
-      const int lpc = banks == 32 ? 32 : 64;
-      for (int e = 0; e < 2; ++e) {
-        std::vector<uint32_t> addr;
-        for (int l = 0; l < 64 && l < nt; ++l) {
-          uint32_t q, c;
-          coords(2u * l + e, q, c);
-          addr.push_back(c * P + q);
-        }
-        cost += degree(addr, lpc);
-      }
-      if (r <= 64) {
-        std::vector<uint32_t> addr;
-        for (uint32_t l = 0; l < 64; ++l) addr.push_back((l >> log2r) * P + (l & (r - 1)));
-        cost += 2 * degree(addr, lpc);
-      } else {
-        std::vector<uint32_t> addr;
-        for (uint32_t l = 0; l < 64; ++l) addr.push_back(l);
-        cost += 2 * degree(addr, lpc);
-      }
-    }
-    cost += 0.01 * pad;  // prefer the smaller pad on ties
-    if (cost < best_cost) {
-      best_cost = cost;
-      best = pad;
-    }
-  }
-  return best;
 }
 
 template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>& a) {
@@ -581,26 +411,9 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   *out = nullptr;
   if (!model || !cfg) return fail(nullptr, PF_E_INVALID, "model or config is NULL");
   const int d = model->d;
-  if (model->kind != PF_MODEL_LG && model->kind != PF_MODEL_SV)
-    return fail(nullptr, PF_E_INVALID, "unknown model kind");
-  if (d < 1 || d > PF_MAX_DIM) return fail(nullptr, PF_E_INVALID, "d must be in [1, 16]");
-  if (model->kind == PF_MODEL_SV) {
-    if (d != 1) return fail(nullptr, PF_E_INVALID, "the SV model has d = 1");
-    if (!(std::fabs(model->phi) < 1.0) || !(model->sigma > 0.0) || !(model->beta > 0.0) ||
-        !std::isfinite(model->sigma) || !std::isfinite(model->beta))
-      return fail(nullptr, PF_E_INVALID, "SV parameters need |phi| < 1, sigma > 0, beta > 0");
-  } else {
-    const double* ms[] = {model->A, model->Q_chol, model->H, model->R_chol, model->P0_chol};
-    for (const double* m : ms)
-      if (!m || !finite_all(m, (size_t)d * d)) return fail(nullptr, PF_E_INVALID, "LG matrix NULL or non-finite");
-    if (!model->m0 || !finite_all(model->m0, d)) return fail(nullptr, PF_E_INVALID, "m0 NULL or non-finite");
-    const double* tri[] = {model->Q_chol, model->R_chol, model->P0_chol};
-    for (const double* L : tri)
-      for (int i = 0; i < d; ++i) {
-        if (!(L[i * d + i] > 0.0)) return fail(nullptr, PF_E_INVALID, "Cholesky factor needs a positive diagonal");
-        for (int j = i + 1; j < d; ++j)
-          if (L[i * d + j] != 0.0) return fail(nullptr, PF_E_INVALID, "Cholesky factor must be lower-triangular");
-      }
+  {
+    std::string msg;
+    if (validate_model(model, msg) != PF_OK) return fail(nullptr, PF_E_INVALID, msg);
   }
   const uint64_t N = cfg->n_particles;
   if (!is_pow2(N) || N < 2 || N > (1ull << 30))
@@ -617,7 +430,7 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   if (!h) return fail(nullptr, PF_E_OOM, "host allocation failed");
   h->kind = model->kind;
   h->d = d;
-  h->D = d <= 1 ? 1 : d <= 2 ? 2 : d <= 4 ? 4 : d <= 8 ? 8 : 16;
+  h->D = compiled_dim(d);
   h->dtype = cfg->state_dtype;
   h->resampler = cfg->resampler;
   h->N = N;

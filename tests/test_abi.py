@@ -57,6 +57,8 @@ def test_struct_layouts_match_header():
                                          "max_log_weight", "next_offset", "mean", "var"]),
         "pf_info_t": ("PfInfo", ["n_particles", "d", "n_stages", "radices", "global_path",
                                  "state_dtype", "device_bytes", "t", "tile_elems"]),
+        "pf_batch_tune_t": ("PfBatchTune", ["class_index", "dim", "model_kind", "pairs_per_thread",
+                                            "radix", "chosen", "ms_per_step", "reserved"]),
     }
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(){"]
     for cname, (_, fl) in fields.items():
@@ -165,3 +167,31 @@ def test_misc_entry_points_without_device(lib):
     n = ctypes.c_uint64(0)
     assert lib.pf_save(None, None, 0, ctypes.byref(n)) == -1
     assert lib.pf_load(None, None, 0) == -1
+
+
+def test_batch_create_rejects_invalid_arguments(lib):
+    """Argument checks of pf_batch_create run before any device work."""
+    from paper_1812_01502_amd import _lib as L
+    m, keep = _model_lg(2)
+    h = ctypes.c_void_p()
+    ms = (L.PfModel * 2)(m, m)
+
+    def cfgs(**kw):
+        arr = (L.PfConfig * 2)()
+        for i in range(2):
+            arr[i] = _cfg(n=kw.get("n", 4096), radix=kw.get("radix", 4))
+            arr[i].state_dtype = kw.get("dtype", 0)
+        return arr
+
+    assert lib.pf_batch_create(ms, cfgs(), 0, None, ctypes.byref(h)) == -1
+    assert lib.pf_batch_create(ms, cfgs(n=256), 2, None, ctypes.byref(h)) == -1
+    assert lib.pf_batch_create(ms, cfgs(radix=128), 2, None, ctypes.byref(h)) == -1
+    assert lib.pf_batch_create(ms, cfgs(radix=3), 2, None, ctypes.byref(h)) == -1
+    assert lib.pf_batch_create(ms, cfgs(dtype=1), 2, None, ctypes.byref(h)) == -2
+    assert b"FP32" in lib.pf_batch_last_error(None)
+    bad = (L.PfModel * 2)(m, m)
+    bad[1].d = 0
+    assert lib.pf_batch_create(bad, cfgs(), 2, None, ctypes.byref(h)) == -1
+    assert b"filter 1" in lib.pf_batch_last_error(None)
+    assert lib.pf_batch_destroy(None) == 0
+    assert lib.pf_batch_step(None, None, None) == -1

@@ -1,0 +1,248 @@
+"""Batched filters (pf_batch_*) on the GPU.
+
+* every filter of a batch computes bit for bit the states and log-weights
+  of a single filter with the same configuration (estimates up to the
+  reduction order);
+* one batched step against the FP64 oracle, teacher-forced, per filter;
+* active masks: an inactive filter is untouched, and a filter gives the
+  same result alone and in the mix;
+* graph replay equals eager stepping; the autotuner's choice is recorded
+  and honoured; a reset slot equals a fresh filter.
+"""
+import numpy as np
+import pytest
+
+import workloads as W
+from oracle import ButterflyOracle, State
+from tests.gpu_util import MARGIN_TOL, log, tolerances
+
+pytestmark = pytest.mark.gpu
+
+
+def _mix():
+    """(model, N, radix) of a mixed batch: three dimension classes of the
+    diagonal-noise LG family, the dense LG model and SV."""
+    return [
+        (W.random_stable_lg(1, 4001), 1024, 2),
+        (W.random_stable_lg(4, 4002), 2048, 8),
+        (W.random_stable_lg(16, 4003), 1024, 64),
+        (W.random_stable_lg(1, 4004), 8192, 64),
+        (W.random_stable_lg(4, 4005), 4096, 4),
+        (W.dense_lg_model(4, 12), 2048, 16),
+        (W.sv_model(), 4096, 32),
+        (W.random_stable_lg(16, 4006), 2048, 2),
+    ]
+
+
+def _packed_obs(models, T, seed=21):
+    ys = [W.simulate(m, T, seed=seed + i)[1] for i, m in enumerate(models)]
+    return np.concatenate([y.reshape(T, -1) for y in ys], axis=1), ys
+
+
+def _batch(spec, seeds=None, active_ok=True):
+    from paper_1812_01502_amd import BatchFilter
+    models = [m for m, _, _ in spec]
+    return BatchFilter(models, [n for _, n, _ in spec], [r for _, _, r in spec],
+                       seeds if seeds is not None else [100 + i for i in range(len(spec))])
+
+
+def _dev(a, dtype):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda").contiguous()
+
+
+def test_batch_equals_single_filters():
+    import torch
+    from paper_1812_01502_amd import Filter
+    spec = _mix()
+    T = 9
+    Y, ys = _packed_obs([m for m, _, _ in spec], T)
+    log(f"[case] batch of {len(spec)} filters vs single filters, {T} steps")
+    b = _batch(spec)
+    yd = _dev(Y, torch.float32)
+    b.run(yd.data_ptr(), T)
+    recs = b.estimates()
+    for i, (m, N, r) in enumerate(spec):
+        f = Filter(m, N, r, seed=100 + i, stream_id=i)
+        y1 = _dev(ys[i].reshape(T, -1), torch.float32)
+        f.run(y1.data_ptr(), T, m.d)
+        xs, ws, ts, lns = f.get_state()
+        xb, wb, tb, lnb = b.get_state(i)
+        assert tb == ts == T
+        assert np.array_equal(xs, xb), (i, "x")
+        assert np.array_equal(ws, wb), (i, "logw")
+        # the estimates and the log-normaliser come from FP32 tile partial
+        # sums, and the tiles of the batch differ from the single filter's:
+        # they agree to FP32 rounding of those sums (a few 2^-24 per step;
+        # the variance loses more where a tile's reference point is far from
+        # the mean)
+        assert abs(lns - lnb) <= 1e-6 * T, (i, lns, lnb)
+        es = f.estimate()
+        eb = recs[i]
+        assert eb["t"] == es["t"] == T - 1 and eb["stage"] == es["stage"] and eb["radix"] == es["radix"]
+        sd = np.sqrt(es["var"])
+        assert np.all(np.abs(eb["mean"] - es["mean"]) <= 1e-5 * np.maximum(np.abs(es["mean"]), sd))
+        assert np.allclose(eb["var"], es["var"], rtol=1e-4)
+        assert abs(eb["ess"] - es["ess"]) <= 1e-4 * es["ess"]
+        info = b.info(i)
+        assert info["stages"] == f.info()["stages"]
+        log(f"   ok filter {i}: d={m.d} N={N} r={r} stages={info['stages']} tile={info['tile']}")
+        f.close()
+    b.close()
+
+
+def test_batch_one_step_against_oracle():
+    """Teacher-forced: each filter starts from the oracle's state (rounded
+    to FP32) at a step whose stage has a wide stride; the step's estimates,
+    new log-weights and states (where the oracle's draw margin exceeds the
+    tolerance) must match the FP64 oracle."""
+    spec = _mix()
+    models = [m for m, _, _ in spec]
+    b = _batch(spec)
+    tol = tolerances("f32")
+    for i, (m, N, r) in enumerate(spec):
+        orc = ButterflyOracle(m, N, r, seed=100 + i, stream_id=i)
+        t = orc.S - 1                      # the most significant digit: widest stride
+        _, ys = W.simulate(m, t + 1, seed=50 + i)
+        st = orc.init()
+        for u in range(t):
+            st, _ = orc.step(st, ys[u], keep=False)
+        x32 = st.x.T.astype(np.float32)
+        w32 = st.logw.astype(np.float32)
+        log(f"[case] batch oracle filter {i}: d={m.d} N={N} r={r} t={t}")
+        b.set_state(i, x32, w32, t=t, log_norm=st.log_norm)
+        ypack = np.zeros(b.y_len, dtype=np.float32)
+        ypack[b.y_offsets[i]:b.y_offsets[i] + m.d] = ys[t]
+        active = np.zeros(b.n, dtype=np.uint8)
+        active[i] = 1
+        import torch
+        yd = _dev(ypack, torch.float32)
+        ad = _dev(active, torch.uint8)
+        b.step(yd.data_ptr(), ad.data_ptr())
+        rec = b.estimates()[i]
+        st0 = State(x=x32.T.astype(np.float64), logw=w32.astype(np.float64), t=t, log_norm=st.log_norm)
+        st1, ro = orc.step(st0, ys[t], keep=True)
+        xg, wg, tg, lng = b.get_state(i)
+        assert tg == t + 1 and rec["t"] == t and rec["stage"] == ro["stage"]
+        assert np.max(np.abs(wg - st1.logw)) <= tol["w_atol"]
+        sd = np.sqrt(ro["var"])
+        assert np.all(np.abs(rec["mean"] - ro["mean"]) <= tol["mean_rtol"] * np.maximum(np.abs(ro["mean"]), sd))
+        assert np.all(np.abs(rec["var"] - ro["var"]) <= tol["var_rtol"] * ro["var"] + 1e-12)
+        assert abs(rec["ess"] - ro["ess"]) <= tol["ess_rtol"] * ro["ess"]
+        assert abs(lng - ro["log_norm"]) <= tol["ln_atol"] * (1 + abs(ro["log_norm"] - st.log_norm))
+        sure = ro["margin"] > MARGIN_TOL
+        err = np.abs(xg.T.astype(np.float64)[sure] - st1.x[sure])
+        lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st1.x[sure])
+        assert np.all(err <= lim), (i, float(np.max(err - lim)))
+        log(f"   ok near={int(np.sum(~sure))} max_dx={float(np.max(err)):.2e}")
+    b.close()
+
+
+def test_active_mask_and_alone_vs_mix():
+    import torch
+    spec = _mix()
+    T = 5
+    Y, _ = _packed_obs([m for m, _, _ in spec], T)
+    yd = _dev(Y, torch.float32)
+    log("[case] batch active mask / alone vs mix")
+    mix = _batch(spec)
+    alone = _batch(spec)
+    j = 5                                   # the dense LG filter
+    only = np.zeros(len(spec), dtype=np.uint8)
+    only[j] = 1
+    od = _dev(only, torch.uint8)
+    x_before = [alone.get_state(i) for i in range(len(spec))]
+    mix.run(yd.data_ptr(), T)
+    alone.run(yd.data_ptr(), T, active_dev_ptr=od.data_ptr())
+    xa, wa, ta, la = alone.get_state(j)
+    xm, wm, tm, lm = mix.get_state(j)
+    assert ta == tm == T and np.array_equal(xa, xm) and np.array_equal(wa, wm) and la == lm
+    recs = alone.estimates()
+    for i in range(len(spec)):
+        if i == j:
+            continue
+        x1, w1, t1, l1 = alone.get_state(i)
+        assert t1 == 0 and np.array_equal(x1, x_before[i][0]) and recs[i]["valid"] == 0
+    mix.close()
+    alone.close()
+
+
+def test_graph_equals_eager_and_reset():
+    import torch
+    from paper_1812_01502_amd import Filter
+    spec = _mix()
+    T = 6
+    Y, ys = _packed_obs([m for m, _, _ in spec], T)
+    yd = _dev(Y, torch.float32)
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    log("[case] batch graph replay vs eager")
+    from paper_1812_01502_amd import BatchFilter
+    models = [m for m, _, _ in spec]
+    eager = _batch(spec)
+    graph = BatchFilter(models, [n for _, n, _ in spec], [r for _, _, r in spec],
+                        [100 + i for i in range(len(spec))], stream=s.cuda_stream)
+    eager.run(yd.data_ptr(), T)
+    with torch.cuda.stream(s):
+        graph.run(yd.data_ptr(), T, use_graph=True)
+    graph.sync()
+    re_, rg = eager.estimates(), graph.estimates()
+    for i in range(len(spec)):
+        a, b_ = eager.get_state(i), graph.get_state(i)
+        assert np.array_equal(a[0], b_[0]) and np.array_equal(a[1], b_[1]) and a[2:] == b_[2:]
+        assert np.array_equal(re_[i]["mean"], rg[i]["mean"]) and re_[i]["log_norm"] == rg[i]["log_norm"]
+    log("[case] batch reset slot")
+    k = 3
+    eager.reset(k, seed=777, stream_id=42)
+    m, N, r = spec[k]
+    f = Filter(m, N, r, seed=777, stream_id=42)
+    y1 = _dev(ys[k].reshape(T, -1), torch.float32)
+    f.run(y1.data_ptr(), T, m.d)
+    only = np.zeros(len(spec), dtype=np.uint8)
+    only[k] = 1
+    od = _dev(only, torch.uint8)
+    eager.run(yd.data_ptr(), T, active_dev_ptr=od.data_ptr())
+    xs, ws, ts, _ = f.get_state()
+    xb, wb, tb, _ = eager.get_state(k)
+    assert ts == tb == T and np.array_equal(xs, xb) and np.array_equal(ws, wb)
+    f.close()
+    eager.close()
+    graph.close()
+
+
+def test_autotuner_choice_recorded_and_honoured():
+    import torch
+    from paper_1812_01502_amd import Filter
+    spec = [(W.random_stable_lg(4, 4010), 4096, 0), (W.random_stable_lg(4, 4011), 2048, 0),
+            (W.random_stable_lg(1, 4012), 1024, 0), (W.random_stable_lg(1, 4013), 4096, 8)]
+    log("[case] batch autotuner")
+    b = _batch(spec)
+    tune = b.tuning()
+    assert tune, "no autotuner trials recorded"
+    chosen = [t for t in tune if t["chosen"]]
+    assert len({t["cls"] for t in chosen}) == len(chosen) == len({t["cls"] for t in tune})
+    for t in tune:
+        assert t["radix"] in (2, 4, 8, 16, 32, 64) and t["ms"] > 0
+    fastest = {}
+    for t in tune:
+        fastest[t["cls"]] = min(fastest.get(t["cls"], 1e9), t["ms"])
+    for t in chosen:
+        assert t["ms"] <= 1.10 * fastest[t["cls"]] + 1e-6
+        log(f"   class {t['cls']} (D={t['dim']}): radix {t['radix']} ppt {t['ppt']} "
+            f"{t['ms'] * 1e3:.1f} us/step (fastest {fastest[t['cls']] * 1e3:.1f})")
+    T = 4
+    Y, ys = _packed_obs([m for m, _, _ in spec], T)
+    yd = _dev(Y, torch.float32)
+    b.run(yd.data_ptr(), T)
+    for i, (m, N, r) in enumerate(spec):
+        info = b.info(i)
+        rr = info["stages"][0] if r == 0 else r
+        if r == 8:
+            assert info["stages"][0] == 8
+        f = Filter(m, N, rr, seed=100 + i, stream_id=i)
+        assert f.info()["stages"] == info["stages"]
+        y1 = _dev(ys[i].reshape(T, -1), torch.float32)
+        f.run(y1.data_ptr(), T, m.d)
+        assert np.array_equal(f.get_state()[0], b.get_state(i)[0])
+        f.close()
+    b.close()
