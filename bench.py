@@ -102,6 +102,57 @@ def cpu_baseline(model, N, radix, ys, budget_s=12.0):
                        f"(stage cycle {orc.plan}), FP64 NumPy, 1 thread, {el:.1f} s")
 
 
+def batched_bench(steps: int, warmup: int):
+    """The batched workload: 4096 independent LG filters, N_f = 2^u with u
+    uniform in 10..16, d_f uniform over {1, 4, 16}, seeded stable A, radix and
+    tile chosen by the autotuner; the timed steps run as one HIP graph."""
+    import numpy as np
+    import torch
+    import paper_1812_01502_amd as P
+    import workloads as W
+    t0 = time.perf_counter()
+    models, Ns, Y = W.batched_workload(T=warmup + steps)
+    gen_s = time.perf_counter() - t0
+    ds = [m.d for m in models]
+    yd = torch.tensor(Y, dtype=torch.float32, device="cuda").contiguous()
+    torch.cuda.synchronize()
+    s = torch.cuda.Stream()
+    t0 = time.perf_counter()
+    b = P.BatchFilter(models, Ns, [0] * len(models), [404 + f for f in range(len(models))],
+                      stream=s.cuda_stream)
+    create_s = time.perf_counter() - t0
+    with torch.cuda.stream(s):
+        b.run(yd.data_ptr(), warmup)
+        b.sync()
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record(s)
+        b.run(yd[warmup:].data_ptr(), steps, use_graph=True)
+        ev1.record(s)
+        b.sync()
+        wall = time.perf_counter() - t0
+    gpu_s = ev0.elapsed_time(ev1) / 1e3
+    recs = b.estimates()
+    tune = b.tuning()
+    b.close()
+    n_part = int(sum(Ns))
+    bytes_step = int(sum(N * (2 * (d * 4 + 4)) for N, d in zip(Ns, ds)))
+    chosen = sorted({(t["dim"], t["radix"], t["ppt"]) for t in tune if t["chosen"]})
+    return {
+        "workload": "4096 LG filters, N in 2^10..2^16, d in {1, 4, 16}, autotuned radix/tile",
+        "filters": len(models), "particles": n_part, "steps": steps,
+        "particle_steps_per_s": n_part * steps / wall,
+        "ms_per_step": wall / steps * 1e3,
+        "graph_gpu_ms_per_step": gpu_s / steps * 1e3,
+        "hbm_frac_algorithmic": bytes_step / (gpu_s / steps) / 1e9 / HBM_PEAK_GBS,
+        "bytes_per_step": bytes_step,
+        "autotuned": [{"dim": d, "radix": r, "tile": 512 * p} for d, r, p in chosen],
+        "create_s": create_s, "input_generation_s": gen_s,
+        "all_valid": bool(all(r["valid"] for r in recs)),
+    }
+
+
 def load_traffic(path, n_launch_bytes):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
@@ -127,6 +178,8 @@ def main():
     ap.add_argument("--extra-radices", default="2,4,32")
     ap.add_argument("--workload", choices=["lg8", "sv"], default="lg8",
                     help="lg8: 8-D LG, N = 2^20 (default); sv: stochastic volatility, N = 2^24")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-filters section")
+    ap.add_argument("--batch-only", action="store_true", help="print only the batched-filters section")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -140,6 +193,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.load_library()
+    if args.batch_only:
+        print(json.dumps({"batched": batched_bench(200, 5)}), flush=True)
+        return
     cfg = W.config("c2" if args.workload == "lg8" else "c3")
     if args.workload == "sv" and args.n == 1 << 20:
         args.n = cfg["N"]
@@ -237,6 +293,8 @@ def main():
         "per_radix": per_radix,
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
     }
+    if not args.no_batch and args.mode == "bench":
+        out["batched"] = batched_bench(200, 5)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(model, N, args.radix, ys)
     print(json.dumps(out), flush=True)

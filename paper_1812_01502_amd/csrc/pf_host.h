@@ -7,7 +7,9 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <string>
+#include <tuple>
 #include <vector>
 
 #include "../../include/pf.h"
@@ -122,7 +124,20 @@ inline void fill_params(const pf_model* m, int d, ModelParams<T>* P, int* mk_out
 // Bank-conflict cost of the LDS pad for the per-group scalar arrays
 // (layout [column][r + pad]): phase-A/C accesses by consecutive pairs and
 // phase-B accesses by group lanes, evaluated for 32 and 64 banks.
+inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt);
+
+// Memoised: the batched planner asks for the same geometries many times.
 inline uint32_t choose_pad(uint32_t r, uint32_t C, uint32_t log2R, int nt) {
+  thread_local std::map<std::tuple<uint32_t, uint32_t, uint32_t, int>, uint32_t> cache;
+  const auto key = std::make_tuple(r, C, log2R, nt);
+  auto it = cache.find(key);
+  if (it != cache.end()) return it->second;
+  const uint32_t p = choose_pad_eval(r, C, log2R, nt);
+  cache.emplace(key, p);
+  return p;
+}
+
+inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) {
   const uint32_t log2r = ilog2(r), log2C = ilog2(C);
   const bool wide = log2R >= log2C;
   auto coords = [&](uint32_t f, uint32_t& q, uint32_t& c) {

@@ -28,7 +28,7 @@ import numpy as np
 __all__ = [
     "ModelSpec", "ar1_model", "lg_model", "lg8_model", "random_stable_lg",
     "dense_lg_model",
-    "sv_model", "random_walk_model", "simulate", "CONFIGS", "config",
+    "sv_model", "random_walk_model", "simulate", "CONFIGS", "config", "batched_workload",
     "haar_orthogonal",
 ]
 
@@ -226,3 +226,16 @@ def batched_filters(n_filters: int = 4096, seed: int = 4):
     ds = np.array([1, 4, 16])[dsel]
     return [dict(N=int(1 << int(uu)), d=int(dd), model_seed=4000 + f)
             for f, (uu, dd) in enumerate(zip(u, ds))]
+
+
+def batched_workload(n_filters: int = 4096, T: int = 200, seed: int = 4):
+    """The batched workload: per-filter models and sizes of
+    ``batched_filters`` and their observations, simulated from each model
+    (seed ``seed * 1_000_000 + f``) and packed per step in filter order.
+    Returns ``(models, Ns, Y)`` with ``Y`` of shape ``(T, sum d_f)``."""
+    spec = batched_filters(n_filters, seed)
+    models = [random_stable_lg(s["d"], s["model_seed"]) for s in spec]
+    Ns = [s["N"] for s in spec]
+    cols = [simulate(m, T, seed=seed * 1_000_000 + f)[1].reshape(T, -1) for f, m in enumerate(models)]
+    return models, Ns, np.concatenate(cols, axis=1)
+
