@@ -153,6 +153,51 @@ def batched_bench(steps: int, warmup: int):
     }
 
 
+def serving_bench(window_s: float = 1.0, rate: float = 2000.0, seed: int = 5):
+    """The serving workload: Poisson arrivals (``rate`` streams/s over
+    ``window_s``) of SV or 4-D LG streams (half each), N uniform over
+    {2^12, 2^16, 2^20}, 50..500 observations each, one observation per
+    millisecond; slot pools sized from the expected concurrency within an
+    HBM budget; continuous batching on one GPU."""
+    import math
+    import numpy as np
+    import workloads as W
+    from paper_1812_01502_amd.serving import Server, StreamRequest, slot_footprint
+    rng = np.random.Generator(np.random.PCG64(seed))
+    models = {"sv": W.sv_model(), "lg4": W.random_stable_lg(4, 5004)}
+    Ns = [1 << 12, 1 << 16, 1 << 20]
+    cadence = 1e-3
+    t, reqs = 0.0, []
+    sim = {}
+    while True:
+        t += rng.exponential(1.0 / rate)
+        if t > window_s:
+            break
+        name = "sv" if rng.random() < 0.5 else "lg4"
+        N = Ns[int(rng.integers(0, 3))]
+        T = int(rng.integers(50, 501))
+        if name not in sim:   # one long simulated path per model; streams take windows of it
+            sim[name] = W.simulate(models[name], 20000, seed=seed)[1].reshape(20000, -1)
+        o = int(rng.integers(0, 20000 - T))
+        reqs.append(StreamRequest(stream_id=len(reqs), model=name, n_particles=N,
+                                  observations=sim[name][o:o + T], arrival_s=t,
+                                  seed=77 + len(reqs), cadence_s=cadence))
+    budget = 24 << 30
+    mean_T = 275.0
+    pools = {}
+    for name in models:
+        for N in Ns:
+            want = math.ceil(1.5 * rate / 6.0 * mean_T * cadence)
+            cap = int((budget / 6) // slot_footprint(models[name].d, N))
+            pools[(name, N)] = max(1, min(want, cap))
+    srv = Server(models, pools, radix=64)
+    _, stats = srv.run(reqs, realtime=True, max_wall_s=300)
+    srv.close()
+    stats.update(workload=f"Poisson {rate:g}/s over {window_s:g} s, SV or LG-4, N in 2^12/2^16/2^20, "
+                          f"50..500 observations at 1 ms", pools={f"{k[0]} N={k[1]}": v for k, v in pools.items()})
+    return stats
+
+
 def load_traffic(path, n_launch_bytes):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
@@ -180,6 +225,9 @@ def main():
                     help="lg8: 8-D LG, N = 2^20 (default); sv: stochastic volatility, N = 2^24")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-filters section")
     ap.add_argument("--batch-only", action="store_true", help="print only the batched-filters section")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
+    ap.add_argument("--serve-only", action="store_true", help="print only the serving section")
+    ap.add_argument("--serve-window", type=float, default=1.0, help="arrival window of the serving run (s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -195,6 +243,9 @@ def main():
     P.load_library()
     if args.batch_only:
         print(json.dumps({"batched": batched_bench(200, 5)}), flush=True)
+        return
+    if args.serve_only:
+        print(json.dumps({"serving": serving_bench(args.serve_window)}), flush=True)
         return
     cfg = W.config("c2" if args.workload == "lg8" else "c3")
     if args.workload == "sv" and args.n == 1 << 20:
@@ -295,6 +346,8 @@ def main():
     }
     if not args.no_batch and args.mode == "bench":
         out["batched"] = batched_bench(200, 5)
+    if not args.no_serve and args.mode == "bench":
+        out["serving"] = serving_bench(args.serve_window)
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(model, N, args.radix, ys)
     print(json.dumps(out), flush=True)

@@ -24,6 +24,14 @@ DTYPES = {"f32": L.PF_DTYPE_F32, "bf16": L.PF_DTYPE_BF16, "f64": L.PF_DTYPE_F64}
 RESAMPLERS = {"multinomial": L.PF_RESAMPLE_MULTINOMIAL, "systematic": L.PF_RESAMPLE_SYSTEMATIC}
 
 
+# NumPy view of pf_estimate_t
+ESTIMATE_DTYPE = np.dtype([("t", np.uint32), ("stage", np.uint32), ("radix", np.uint32),
+                           ("valid", np.uint32), ("log_normaliser", np.float64), ("ess", np.float64),
+                           ("max_log_weight", np.float64), ("next_offset", np.float64),
+                           ("mean", np.float64, (L.PF_MAX_DIM,)), ("var", np.float64, (L.PF_MAX_DIM,))])
+assert ESTIMATE_DTYPE.itemsize == ctypes.sizeof(L.PfEstimate)
+
+
 class PfError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{L.STATUS_NAMES.get(status, status)}: {msg}")
@@ -283,6 +291,13 @@ class BatchFilter:
         recs = (L.PfEstimate * self.n)()
         self._check(self._lib.pf_batch_estimates(self._h, recs))
         return [Filter._rec(recs[i], self.ds[i]) for i in range(self.n)]
+
+    def estimates_array(self, out: np.ndarray | None = None) -> np.ndarray:
+        """Records of every filter as a NumPy structured array (``ESTIMATE_DTYPE``)."""
+        if out is None:
+            out = np.empty(self.n, dtype=ESTIMATE_DTYPE)
+        self._check(self._lib.pf_batch_estimates(self._h, out.ctypes.data_as(ctypes.POINTER(L.PfEstimate))))
+        return out
 
     def info(self, f: int) -> dict:
         i = L.PfInfo()
