@@ -237,17 +237,21 @@ template <int D, typename T> struct Model<D, MK_LG_DENSE, T> {
     }
     return P->lconst - (T)0.5 * qf;
   }
+  // component j of f(xh, z): needs z[0..j] (Lq is lower-triangular)
+  static __device__ __forceinline__ T row(const ModelParams<T>* __restrict__ P, const T (&xh)[D],
+                                          const T (&z)[D], const int j) {
+    T v = 0;
+#pragma unroll
+    for (int k = 0; k < D; ++k) v += P->A[j * kMaxDim + k] * xh[k];
+#pragma unroll
+    for (int k = 0; k < D; ++k)
+      if (k <= j) v += P->Lq[j * kMaxDim + k] * z[k];
+    return v;
+  }
   static __device__ __forceinline__ void propagate(const ModelParams<T>* __restrict__ P,
                                                    const T (&xh)[D], const T (&z)[D], T (&xo)[D]) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T v = 0;
-#pragma unroll
-      for (int k = 0; k < D; ++k) v += P->A[j * kMaxDim + k] * xh[k];
-#pragma unroll
-      for (int k = 0; k <= j; ++k) v += P->Lq[j * kMaxDim + k] * z[k];
-      xo[j] = v;
-    }
+    for (int j = 0; j < D; ++j) xo[j] = row(P, xh, z, j);
   }
   static __device__ __forceinline__ void prior(const ModelParams<T>* __restrict__ P, const T (&z)[D],
                                                T (&xo)[D]) {
@@ -272,15 +276,18 @@ template <int D, typename T> struct Model<D, MK_LG_DIAG, T> {
     }
     return P->lconst - (T)0.5 * qf;
   }
+  // component j of f(xh, z): needs z[j] only
+  static __device__ __forceinline__ T row(const ModelParams<T>* __restrict__ P, const T (&xh)[D],
+                                          const T (&z)[D], const int j) {
+    T v = P->qd[j] * z[j];
+#pragma unroll
+    for (int k = 0; k < D; ++k) v += P->A[j * kMaxDim + k] * xh[k];
+    return v;
+  }
   static __device__ __forceinline__ void propagate(const ModelParams<T>* __restrict__ P,
                                                    const T (&xh)[D], const T (&z)[D], T (&xo)[D]) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) {
-      T v = P->qd[j] * z[j];
-#pragma unroll
-      for (int k = 0; k < D; ++k) v += P->A[j * kMaxDim + k] * xh[k];
-      xo[j] = v;
-    }
+    for (int j = 0; j < D; ++j) xo[j] = row(P, xh, z, j);
   }
   static __device__ __forceinline__ void prior(const ModelParams<T>* __restrict__ P, const T (&z)[D],
                                                T (&xo)[D]) {
@@ -294,9 +301,13 @@ template <int D, typename T> struct Model<D, MK_SV, T> {
                                             const T (&y)[D]) {
     return P->lconst - (T)0.5 * x[0] - y[0] * y[0] * fexp(-x[0]) * P->inv2b2;
   }
+  static __device__ __forceinline__ T row(const ModelParams<T>* __restrict__ P, const T (&xh)[D],
+                                          const T (&z)[D], const int) {
+    return P->phi * xh[0] + P->sigma * z[0];
+  }
   static __device__ __forceinline__ void propagate(const ModelParams<T>* __restrict__ P,
                                                    const T (&xh)[D], const T (&z)[D], T (&xo)[D]) {
-    xo[0] = P->phi * xh[0] + P->sigma * z[0];
+    xo[0] = row(P, xh, z, 0);
   }
   static __device__ __forceinline__ void prior(const ModelParams<T>* __restrict__ P, const T (&z)[D],
                                                T (&xo)[D]) {
@@ -316,12 +327,16 @@ constexpr int kOffSlots = 32;
 constexpr int kOffStride = 16;   // 16 x 8 B = one 128-B line per slot
 constexpr int kOffRing = 3;
 constexpr int kOffEntries = kOffRing * kOffSlots * kOffStride;
+// Steps whose reductions may be deferred and done together.
+constexpr int kMaxPending = 64;
 
 struct Ctl {
   double log_norm;           // running log-normaliser (FP64)
   uint32_t t;                // steps reduced so far (diagnostic)
   uint32_t pad[13];
   long long offs[kOffEntries];  // encoded maxima, [ring][slot * stride]
+  double step_off[kMaxPending]; // offset step t subtracted, at t mod kMaxPending
+  double dlog[kMaxPending];     // log-normaliser increments of deferred reductions
 };
 
 // Per-tile partial record: [m, S, sw2, swin, A1[D], A2[D], sh[D]].

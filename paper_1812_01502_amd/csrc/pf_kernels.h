@@ -34,8 +34,6 @@ template <typename T, typename S> struct StepArgs {
   T y_val[kMaxDim];         // observation passed by value when y_dev == nullptr
   const ModelParams<T>* mp;
   T* part_out;              // tile partials of this step
-  const T* part_prev;       // nullable: partials of the previous step, still to reduce
-  uint32_t ntiles_prev, t_prev, k_prev, radix_prev;
   Ctl* ctl;
   pf_estimate_t* hist;
   uint32_t hist_cap;
@@ -148,6 +146,11 @@ struct FinArgs {
   pf_estimate_t* hist;
   uint32_t hist_cap, t, k, radix, d;
   uint64_t N;
+  // deferred reductions: the increment goes to ctl->dlog[slot] and the
+  // running log-normaliser is added by a later pass; write_rec = 0 skips the
+  // record (a later step owns its history slot); the next offset comes from
+  // the following step's bookkeeping (use_step_off) or from the slots
+  uint32_t multi, slot, write_rec, use_step_off;
 };
 
 // FP64 reduction of one step's tile partials by one block, in a fixed order.
@@ -180,8 +183,12 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
   // up front: they are only needed at the end
   double offv = -INFINITY, ln0 = 0.0;
   if (wv == 0) {
-    if (lane < kOffSlots) offv = ord_decode(*off_slot(f.ctl, f.t + 1, lane));
-    if (lane == 0) ln0 = f.ctl->log_norm;
+    if (f.use_step_off) {
+      if (lane == 0) offv = f.ctl->step_off[(f.t + 1) % kMaxPending];
+    } else if (lane < kOffSlots) {
+      offv = ord_decode(*off_slot(f.ctl, f.t + 1, lane));
+    }
+    if (lane == 0 && !f.multi) ln0 = f.ctl->log_norm;
   }
   double mt = -INFINITY, swin = 0.0, s = 0.0, sw2 = 0.0, a1[D], a2[D];
 #pragma unroll
@@ -277,7 +284,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
   const double mx = __shfl(tv, 4 + jl, 64), mxx = __shfl(tv, 4 + D + jl, 64);
   const double nx = wave_max(offv);
   pf_estimate_t* rec = f.hist + (f.t % f.hist_cap);
-  if (lane < kMaxDim) {
+  if (f.write_rec && lane < kMaxDim) {
     double mean = 0.0, var = 0.0;
     if (lane < D && lane < d) {
       mean = mx / S;
@@ -287,17 +294,24 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
     rec->var[lane] = var;
   }
   if (lane == 0) {
-    const double ln = ln0 + ((M + log(S)) - log(swin_t));
-    rec->t = f.t;
-    rec->stage = f.k;
-    rec->radix = f.radix;
-    rec->valid = 1u;
-    rec->log_normaliser = ln;
-    rec->ess = S * S / ((double)f.N * sw2_t);
-    rec->max_log_weight = M;
-    rec->next_offset = nx;
-    f.ctl->log_norm = ln;
-    f.ctl->t = f.t + 1;
+    const double dlog = (M + log(S)) - log(swin_t);
+    const double ln = ln0 + dlog;
+    if (f.write_rec) {
+      rec->t = f.t;
+      rec->stage = f.k;
+      rec->radix = f.radix;
+      rec->valid = 1u;
+      rec->log_normaliser = f.multi ? 0.0 : ln;
+      rec->ess = S * S / ((double)f.N * sw2_t);
+      rec->max_log_weight = M;
+      rec->next_offset = nx;
+    }
+    if (f.multi) {
+      f.ctl->dlog[f.slot] = dlog;
+    } else {
+      f.ctl->log_norm = ln;
+      f.ctl->t = f.t + 1;
+    }
   }
 }
 
@@ -308,25 +322,66 @@ __global__ void __launch_bounds__(NT) pf_finalize_kernel(FinArgs f, const T* par
   finalize_partials<D, T, NT, fin_batch<D, T>()>(f, part, ntiles, red);
 }
 
-template <typename T, typename S> __device__ __forceinline__ FinArgs prev_fin_args(const StepArgs<T, S>& a) {
+// Several deferred steps at once: block i reduces step fm.steps[i] (its
+// partials in ring slot t mod fm.ring); a second launch adds the running
+// log-normaliser in step order.
+struct FinStep {
+  uint32_t t, k, radix, ntiles;
+};
+struct FinMulti {
+  Ctl* ctl;
+  pf_estimate_t* hist;
+  const void* part_base;
+  uint64_t part_stride;  // elements per ring slot
+  uint64_t N;
+  uint32_t hist_cap, d, n, ring;
+  FinStep steps[kMaxPending];
+};
+
+template <int D, typename T, int NT>
+__global__ void __launch_bounds__(NT) pf_finalize_multi(FinMulti fm) {
+  __shared__ double red[(NT / 64) * (4 + 2 * D)];
+  const uint32_t i = blockIdx.x;
+  const FinStep st = fm.steps[i];
   FinArgs f;
-  f.ctl = a.ctl;
-  f.hist = a.hist;
-  f.hist_cap = a.hist_cap;
-  f.t = a.t_prev;
-  f.k = a.k_prev;
-  f.radix = a.radix_prev;
-  f.d = a.d;
-  f.N = a.N;
-  return f;
+  f.ctl = fm.ctl;
+  f.hist = fm.hist;
+  f.hist_cap = fm.hist_cap;
+  f.t = st.t;
+  f.k = st.k;
+  f.radix = st.radix;
+  f.d = fm.d;
+  f.N = fm.N;
+  f.multi = 1u;
+  f.slot = i;
+  f.write_rec = (fm.n - 1u - i) < fm.hist_cap ? 1u : 0u;
+  f.use_step_off = (i + 1u < fm.n) ? 1u : 0u;
+  const T* part = reinterpret_cast<const T*>(fm.part_base) + (size_t)(st.t % fm.ring) * fm.part_stride;
+  finalize_partials<D, T, NT, fin_batch<D, T>()>(f, part, st.ntiles, red);
 }
 
-// Block 0 of a step kernel: reduce the previous step's partials, and clear
-// the offset slot that the next step will accumulate into.
-template <int D, typename T, typename S, int NT>
-__device__ void step_head_block(const StepArgs<T, S>& a, double* red) {
+template <typename T>
+__global__ void __launch_bounds__(64) pf_finalize_prefix(FinMulti fm) {
+  if (threadIdx.x != 0) return;
+  double ln = fm.ctl->log_norm;
+  for (uint32_t i = 0; i < fm.n; ++i) {
+    ln += fm.ctl->dlog[i];
+    if (fm.n - 1u - i < fm.hist_cap) fm.hist[fm.steps[i].t % fm.hist_cap].log_normaliser = ln;
+  }
+  fm.ctl->log_norm = ln;
+  fm.ctl->t = fm.steps[fm.n - 1u].t + 1u;
+}
+
+// Per-step bookkeeping by block 0 of a step: record the offset this step
+// subtracts (the previous step's next offset, for deferred reductions) and
+// clear the offset slots that the next step will gather into.
+template <typename T, typename S>
+__device__ __forceinline__ void step_bookkeeping(const StepArgs<T, S>& a) {
+  if (threadIdx.x < 64u) {
+    const double o = read_offset(a.ctl, a.t);
+    if (threadIdx.x == 0) a.ctl->step_off[a.t % kMaxPending] = o;
+  }
   clear_offset(a.ctl, a.t + 2, -INFINITY);
-  if (a.part_prev) finalize_partials<D, T, NT, 1>(prev_fin_args(a), a.part_prev, a.ntiles_prev, red);
 }
 
 // Partial sums of one tile from per-thread register values (relative to the
@@ -437,7 +492,7 @@ __device__ __forceinline__ void tile_coords(const TileGeo& g, uint32_t f, uint32
   }
 }
 
-// Tile index of block b (1..nb; block 0 is the head block). Blocks are dealt
+// Tile index of block b. Blocks are dealt
 // round-robin to the 8 XCDs; each XCD gets a contiguous range of tiles, so
 // neighbouring column chunks share the XCD's L2.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
@@ -477,8 +532,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint3
     add(C * tsz);         // column total
     add(C * tsz);         // first member's uniform
   }
-  const size_t fin = (size_t)(NT / 64) * (4 + 2 * D) * 8;  // head block: finalize scratch
-  return b > fin ? b : fin;
+  return b;
 }
 
 // ---------------------------------------------------------------------------
@@ -743,55 +797,67 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
-  // ---- phase C: remaining normals, gather, propagate, store ----------------
+  // ---- phase C: gather, then per Philox block: normals, propagate, store ---
+  // each component is stored as soon as its normals exist, so only the
+  // gathered states (and, for a dense noise factor, the normals so far)
+  // stay live
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const uint32_t f0 = 2u * (tid + it * NT);
-    T z[2][D], xo[2][D], lwo[2];
-#pragma unroll
-    for (int j = 0; j < D; ++j) z[0][j] = z[1][j] = 0;
-    z[0][0] = z0r[2 * it];
-    z[1][0] = z0r[2 * it + 1];
-    uint64_t g0 = 0;
+    T xh[2][D], z[2][D], lwo[2];
     uint32_t ai[2];
+    uint64_t g0 = 0;
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
       uint32_t q, c;
       uint64_t gi;
-      tile_coords(geo, f0 + e, q, c, gi);
-      if (e == 0) {
-        g0 = gi;
-        pair_normals_rest<D, T>((uint32_t)(g0 >> 1), tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
-      }
+      tile_coords(geo, f0 + e, q, c, gi);  // the pair is gi = g0, g0 + 1
+      if (e == 0) g0 = gi;
       const uint32_t pos = (uint32_t)sca[c * P + q];
-      T xh[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j) xh[j] = (j < d) ? xs[(size_t)j * E + (pos << log2C) + c] : (T)0;
-      Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
+      for (int j = 0; j < D; ++j) {
+        xh[e][j] = (j < d) ? xs[(size_t)j * E + (pos << log2C) + c] : (T)0;
+        z[e][j] = 0;
+      }
       lwo[e] = colw[c];
       ai[e] = (uint32_t)((int64_t)gi + ((int64_t)pos - (int64_t)q) * ((int64_t)1 << a.log2R));
     }
-#pragma unroll
-    for (int j = 0; j < D; ++j)
-      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + g0, xo[0][j], xo[1][j]);
     Pair<T, T>::store(a.lw_out + g0, lwo[0], lwo[1]);
     if (a.anc) {
       a.anc[g0] = ai[0];
       a.anc[g0 + 1] = ai[1];
     }
+    z[0][0] = z0r[2 * it];
+    z[1][0] = z0r[2 * it + 1];
+    Pair<S, T>::store(a.x_out + g0, Model<D, MK, T>::row(a.mp, xh[0], z[0], 0),
+                      Model<D, MK, T>::row(a.mp, xh[1], z[1], 0));
+    const uint32_t pr = (uint32_t)(g0 >> 1);
+#pragma unroll
+    for (int b = 1; 2 * b - 1 < D; ++b) {
+      if (2 * b - 1 < d) {
+        const Words w = philox(pr, tau, (uint32_t)b, a.sid, a.k0, a.k1);
+        box_muller(w.w0, w.w1, z[0][2 * b - 1], z[1][2 * b - 1]);
+        Pair<S, T>::store(a.x_out + (size_t)(2 * b - 1) * N + g0,
+                          Model<D, MK, T>::row(a.mp, xh[0], z[0], 2 * b - 1),
+                          Model<D, MK, T>::row(a.mp, xh[1], z[1], 2 * b - 1));
+        if (2 * b < D && 2 * b < d) {
+          box_muller(w.w2, w.w3, z[0][2 * b], z[1][2 * b]);
+          Pair<S, T>::store(a.x_out + (size_t)(2 * b) * N + g0,
+                            Model<D, MK, T>::row(a.mp, xh[0], z[0], 2 * b),
+                            Model<D, MK, T>::row(a.mp, xh[1], z[1], 2 * b));
+        }
+      }
+    }
   }
 }
 
-// Single filter: block 0 is the head block (reduction of the previous
-// step); block b >= 1 processes tile xcd_tile(b - 1).
+// Single filter: block b processes tile xcd_tile(b); block 0 also does the
+// step's bookkeeping.
 template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
 __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
-  if (blockIdx.x == 0) {
-    step_head_block<D, T, S, NT>(a, reinterpret_cast<double*>(smem));
-    return;
-  }
-  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH>(a, xcd_tile(blockIdx.x - 1u, a.ntiles), smem);
+  if (blockIdx.x == 0) step_bookkeeping(a);
+  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH>(a, xcd_tile(blockIdx.x, a.ntiles), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -848,7 +914,6 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   a.y_dev = ba.y + F.yoff;
   a.mp = F.mp;
   a.part_out = F.part;
-  a.part_prev = nullptr;
   a.ctl = F.ctl;
   a.hist = F.rec;
   a.hist_cap = 1u;
@@ -889,6 +954,10 @@ __global__ void __launch_bounds__(NT) pf_batch_finalize(BatchArgs ba) {
   fa.radix = 1u << ba.stages[F.stage0 + k].log2r;
   fa.d = F.d;
   fa.N = F.N;
+  fa.multi = 0u;
+  fa.slot = 0u;
+  fa.write_rec = 1u;
+  fa.use_step_off = 0u;
   finalize_partials<D, float, NT, fin_batch<D, float>()>(fa, F.part, F.ntiles, red);
   if (threadIdx.x < 64u) {
     clear_offset(F.ctl, t + 2u, -INFINITY);
@@ -898,25 +967,19 @@ __global__ void __launch_bounds__(NT) pf_batch_finalize(BatchArgs ba) {
 
 // ---------------------------------------------------------------------------
 // Global path, kernel 1: log-weights, tile max, tile inclusive CDF and
-// estimate partials. Every thread owns NLOC contiguous particles. Block 0
-// is the head block (previous step's reduction).
+// estimate partials. Every thread owns NLOC contiguous particles.
 // ---------------------------------------------------------------------------
 template <int D, int MK, typename T, typename S, int NT, int PPT>
 __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   constexpr int NLOC = 2 * PPT;
   constexpr int PS = partial_stride(D);
   constexpr uint32_t E = 2u * NT * PPT;
-  __shared__ double fin_red[(NT / 64) * (4 + 2 * D)];
   __shared__ T red[(NT / 64) * PS];
   __shared__ T wtot[NT / 64];
   __shared__ T shx[D];
-  if (blockIdx.x == 0) {
-    step_head_block<D, T, S, NT>(a, fin_red);
-    return;
-  }
   const int d = (int)a.d;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const uint32_t tile = blockIdx.x - 1u;
+  const uint32_t tile = blockIdx.x;
   const uint64_t base = (uint64_t)tile * E + (uint64_t)tid * NLOC;
   const uint64_t N = a.N;
   T y[D];
@@ -1024,6 +1087,7 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   }
   if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
   if (tid == 0) *off_slot(a.ctl, a.t + 1, 0) = ord_encode(0.0);
+  step_bookkeeping(a);
 }
 
 // Global path, kernel 3: inverse-CDF draw over the whole population (tile

@@ -15,7 +15,9 @@ enum LaunchWhat : int {
   LW_GLOBAL_WEIGHT = 2,
   LW_GLOBAL_PREFIX = 3,
   LW_GLOBAL_DRAW = 4,
-  LW_FINALIZE = 5
+  LW_FINALIZE = 5,
+  LW_FINALIZE_MULTI = 6,
+  LW_FINALIZE_PREFIX = 7
 };
 
 // What the runtime asks for.
@@ -33,11 +35,13 @@ struct LaunchReq {
   FinArgs fin;
   const void* fin_part;
   uint32_t fin_ntiles;
+  // deferred reductions (LW_FINALIZE_MULTI / LW_FINALIZE_PREFIX)
+  const FinMulti* fm;
 };
 
 // Pairs per thread of the butterfly wave path (256 threads) by dimension:
 // keeps the registers held across the step (states, normals) bounded.
-constexpr int ppt_wave(int D) { return D <= 2 ? 4 : (D <= 8 ? 2 : 1); }
+constexpr int ppt_wave(int D) { return D <= 2 ? 4 : 1; }
 // Pairs per thread of the butterfly block path (256 threads): tiles of
 // 512 PPT particles hold at least two groups of r <= 256 PPT.
 constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 : 1)); }
@@ -141,6 +145,14 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(1), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    case LW_FINALIZE_MULTI: {
+      hipLaunchKernelGGL((pf_finalize_multi<D, T, 512>), dim3(rq.fm->n), dim3(512), 0, st, *rq.fm);
+      return hipGetLastError();
+    }
+    case LW_FINALIZE_PREFIX: {
+      hipLaunchKernelGGL((pf_finalize_prefix<T>), dim3(1), dim3(64), 0, st, *rq.fm);
       return hipGetLastError();
     }
     case LW_FINALIZE: {

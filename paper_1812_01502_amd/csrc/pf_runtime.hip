@@ -36,10 +36,12 @@ struct pf_handle {
   void* lw[2] = {nullptr, nullptr};
   int cur = 0;
   void* mp = nullptr;        // ModelParams<T>
-  void* partials[2] = {nullptr, nullptr};  // tile partials by step parity
-  // the last step whose partials have not been reduced yet
-  bool fin_pending = false;
-  uint32_t pend_t = 0, pend_k = 0, pend_radix = 0, pend_ntiles = 0;
+  // tile partials: a ring of `ring` steps, part_stride elements each
+  void* partials = nullptr;
+  uint32_t ring = 1;
+  uint64_t part_stride = 0;
+  // steps whose partials have not been reduced yet (oldest first)
+  std::vector<FinStep> pending;
   Ctl* ctl = nullptr;
   pf_estimate_t* hist = nullptr;
   uint32_t hist_cap = 1;
@@ -119,14 +121,7 @@ template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>&
   a.lw_out = reinterpret_cast<T*>(h->lw[h->cur ^ 1]);
   a.anc = h->anc;
   a.mp = reinterpret_cast<const ModelParams<T>*>(h->mp);
-  a.part_out = reinterpret_cast<T*>(h->partials[h->t & 1]);
-  if (h->fin_pending) {
-    a.part_prev = reinterpret_cast<const T*>(h->partials[h->pend_t & 1]);
-    a.ntiles_prev = h->pend_ntiles;
-    a.t_prev = h->pend_t;
-    a.k_prev = h->pend_k;
-    a.radix_prev = h->pend_radix;
-  }
+  a.part_out = reinterpret_cast<T*>(h->partials) + (size_t)(h->t % h->ring) * h->part_stride;
   a.ctl = h->ctl;
   a.hist = h->hist;
   a.hist_cap = h->hist_cap;
@@ -161,9 +156,11 @@ pf_status run_init(pf_handle* h) {
   if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
   h->t = 0;
   h->lw_zero = true;
-  h->fin_pending = false;
+  h->pending.clear();
   return PF_OK;
 }
+
+pf_status flush(pf_handle* h);
 
 // One time step; y either by value (y_host) or in device memory (y_dev).
 template <typename T, typename S>
@@ -196,7 +193,7 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.nt = sp.nt;
     rq.ppt = sp.ppt;
     rq.blockpath = sp.blockpath;
-    rq.grid = sp.ntiles + 1;  // block 0 reduces the previous step
+    rq.grid = sp.ntiles;
     rq.lds = sp.lds;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
@@ -209,7 +206,7 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.what = LW_GLOBAL_WEIGHT;
     rq.nt = (int)h->g_nt;
     rq.ppt = (int)h->g_ppt;
-    rq.grid = h->g_ntiles + 1;  // block 0 reduces the previous step
+    rq.grid = h->g_ntiles;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global weight launch");
     rq.what = LW_GLOBAL_PREFIX;
@@ -231,38 +228,70 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
   // the global path does not store log-weights: after it every one is 0
   h->cur ^= 1;
   h->lw_zero = h->global;
-  h->fin_pending = true;
-  h->pend_t = (uint32_t)h->t;
-  h->pend_k = k;
-  h->pend_radix = h->global ? (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu) : sp.r;
-  h->pend_ntiles = h->global ? h->g_ntiles : sp.ntiles;
+  FinStep fs;
+  fs.t = (uint32_t)h->t;
+  fs.k = k;
+  fs.radix = h->global ? (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu) : sp.r;
+  fs.ntiles = h->global ? h->g_ntiles : sp.ntiles;
+  h->pending.push_back(fs);
   h->t += 1;
+  // the ring of partials is full: reduce the pending steps now
+  if (h->pending.size() >= h->ring) return flush(h);
   return PF_OK;
 }
 
-// Reduce the last step's partials (estimate record, log-normaliser).
+// Reduce the pending steps' partials (estimate records, log-normaliser):
+// one step with the complete single-block reduction, several with one
+// block per step and a pass adding the log-normaliser in step order.
 pf_status flush(pf_handle* h) {
-  if (!h->fin_pending) return PF_OK;
+  const size_t n = h->pending.size();
+  if (n == 0) return PF_OK;
+  char dummy[sizeof(StepArgs<double, double>)] = {0};  // dispatch only reads the request
   LaunchReq rq{};
-  rq.what = LW_FINALIZE;
   rq.D = h->D;
   rq.mk = h->mk;
   rq.grid = 1;
-  rq.fin.ctl = h->ctl;
-  rq.fin.hist = h->hist;
-  rq.fin.hist_cap = h->hist_cap;
-  rq.fin.t = h->pend_t;
-  rq.fin.k = h->pend_k;
-  rq.fin.radix = h->pend_radix;
-  rq.fin.d = (uint32_t)h->d;
-  rq.fin.N = h->N;
-  rq.fin_part = h->partials[h->pend_t & 1];
-  rq.fin_ntiles = h->pend_ntiles;
-  // any StepArgs will do for the dispatch; only the request is read
-  char dummy[sizeof(StepArgs<double, double>)] = {0};
-  hipError_t e = launch(h, rq, dummy);
-  if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
-  h->fin_pending = false;
+  if (n == 1) {
+    const FinStep& fs = h->pending[0];
+    rq.what = LW_FINALIZE;
+    rq.fin.ctl = h->ctl;
+    rq.fin.hist = h->hist;
+    rq.fin.hist_cap = h->hist_cap;
+    rq.fin.t = fs.t;
+    rq.fin.k = fs.k;
+    rq.fin.radix = fs.radix;
+    rq.fin.d = (uint32_t)h->d;
+    rq.fin.N = h->N;
+    rq.fin.multi = 0u;
+    rq.fin.slot = 0u;
+    rq.fin.write_rec = 1u;
+    rq.fin.use_step_off = 0u;
+    rq.fin_part = reinterpret_cast<const char*>(h->partials) + (size_t)(fs.t % h->ring) * h->part_stride * h->tsz;
+    rq.fin_ntiles = fs.ntiles;
+    hipError_t e = launch(h, rq, dummy);
+    if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+  } else {
+    FinMulti fm;
+    std::memset(&fm, 0, sizeof(fm));
+    fm.ctl = h->ctl;
+    fm.hist = h->hist;
+    fm.part_base = h->partials;
+    fm.part_stride = h->part_stride;
+    fm.N = h->N;
+    fm.hist_cap = h->hist_cap;
+    fm.d = (uint32_t)h->d;
+    fm.n = (uint32_t)n;
+    fm.ring = h->ring;
+    for (size_t i = 0; i < n; ++i) fm.steps[i] = h->pending[i];
+    rq.fm = &fm;
+    rq.what = LW_FINALIZE_MULTI;
+    hipError_t e = launch(h, rq, dummy);
+    if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+    rq.what = LW_FINALIZE_PREFIX;
+    e = launch(h, rq, dummy);
+    if (e != hipSuccess) return hip_fail(h, e, "finalize launch");
+  }
+  h->pending.clear();
   return PF_OK;
 }
 
@@ -476,9 +505,14 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   }
   uint32_t max_tiles = h->global ? h->g_ntiles : 0;
   for (auto& sp : h->stages) max_tiles = std::max(max_tiles, sp.ntiles);
-  for (int i = 0; i < 2; ++i)
-    if ((s = dalloc(h, &h->partials[i], (size_t)max_tiles * partial_stride(h->D) * h->tsz)) != PF_OK)
-      return bail(s);
+  // ring of deferred partials: up to kMaxPending steps within 64 MiB
+  h->part_stride = (uint64_t)max_tiles * partial_stride(h->D);
+  {
+    const uint64_t per = h->part_stride * h->tsz;
+    const uint64_t fit = (64ull << 20) / (per ? per : 1);
+    h->ring = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxPending, fit));
+  }
+  if ((s = dalloc(h, &h->partials, (size_t)h->ring * h->part_stride * h->tsz)) != PF_OK) return bail(s);
   void* p = nullptr;
   if ((s = dalloc(h, &p, sizeof(Ctl))) != PF_OK) return bail(s);
   h->ctl = reinterpret_cast<Ctl*>(p);
@@ -673,7 +707,7 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
   c.offs[(t % kOffRing) * kOffSlots * kOffStride] = ord_encode(0.0);
   c.t = t;
-  h->fin_pending = false;
+  h->pending.clear();
   e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "control upload");
   h->t = t;
@@ -767,7 +801,7 @@ pf_status pf_load(pf_handle* h, const void* buf, uint64_t len) {
   in += lb;
   h->lw_zero = hd.lw_zero != 0;
   h->t = hd.t;
-  h->fin_pending = false;
+  h->pending.clear();
   Ctl c;
   e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "control copy");

@@ -55,11 +55,15 @@ class StreamResult:
     final_state: tuple = None          # (x, logw, t, log_norm) if requested
 
 
+CTL_BYTES = 13376    # control block: log-normaliser, offset slots, deferred increments
+PARAM_BYTES = 5332   # FP32 model parameters
+
+
 def slot_footprint(d: int, n: int) -> int:
     """Device bytes of one slot: double-buffered states and log-weights,
     tile partial records, control block, model parameters, record."""
     D = 1 if d <= 1 else 2 if d <= 2 else 4 if d <= 4 else 8 if d <= 8 else 16
-    return 2 * d * n * 4 + 2 * n * 4 + (n // 512) * (4 + 3 * D) * 4 + 12800 + 5632 + 304
+    return 2 * d * n * 4 + 2 * n * 4 + (n // 512) * (4 + 3 * D) * 4 + CTL_BYTES + PARAM_BYTES + 304
 
 
 def slots_for_budget(shapes: dict, dims: dict, hbm_budget: int) -> dict:
