@@ -35,8 +35,15 @@ def _hipcc() -> str:
     return p
 
 
+# Kernel translation units assume no NaN operands (the host validates model
+# parameters and host observations): max/min need no NaN quieting. The host
+# runtime keeps IEEE NaN semantics for its own checks.
+KERNEL_FLAGS = ["-fno-honor-nans"]
+
+
 def _compile(src: str, obj: str) -> None:
-    cmd = [_hipcc(), *HIP_FLAGS, "-c", src, "-o", obj]
+    extra = KERNEL_FLAGS if os.path.basename(src).startswith("pf_kernels_") else []
+    cmd = [_hipcc(), *HIP_FLAGS, *extra, "-c", src, "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {os.path.basename(src)}:\n{r.stderr[-6000:]}")

@@ -93,6 +93,10 @@ __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
 __device__ __forceinline__ double flog(double x) { return log(x); }
+// ln x for x >= 1 (a group's weight total relative to its largest member):
+// the hardware log2 needs no denormal scaling there.
+__device__ __forceinline__ float flog_ge1(float x) { return __builtin_amdgcn_logf(x) * 0.693147180559945f; }
+__device__ __forceinline__ double flog_ge1(double x) { return log(x); }
 __device__ __forceinline__ float fmaxT(float a, float b) { return fmaxf(a, b); }
 __device__ __forceinline__ double fmaxT(double a, double b) { return fmax(a, b); }
 

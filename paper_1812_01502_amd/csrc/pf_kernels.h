@@ -595,6 +595,168 @@ __device__ __forceinline__ double seg_scan(double v, uint32_t lr, uint32_t q) {
 }
 
 // ---------------------------------------------------------------------------
+// Groups of r = 2^LR lanes with LR known at compile time (the wave path).
+// FP32: DPP lane moves that the compiler fuses into the max / add; the
+// value of a group's first or last lane is read with readlane when a group
+// is half of the wave or all of it, else with a bpermute.
+// ---------------------------------------------------------------------------
+template <int CTRL, int RM, bool BC>
+__device__ __forceinline__ float dppx(float old, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
+                                                                __builtin_bit_cast(int, v), CTRL, RM, 0xF, BC));
+}
+// lane move with every lane's source valid (quad permutes, mirrors): no old
+// value, so the compiler can fuse it into the consuming max
+template <int CTRL> __device__ __forceinline__ float dppm(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ float rdlane(float v, int l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
+}
+__device__ __forceinline__ float bperm(uint32_t byte_addr, float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((int)byte_addr, __builtin_bit_cast(int, v)));
+}
+
+template <int LR, typename T> struct Grp;
+
+template <int LR> struct Grp<LR, float> {
+  static constexpr uint32_t r = 1u << LR;
+  // max over the group, in every lane of the group
+  static __device__ __forceinline__ float max(float v, uint32_t lane) {
+    if constexpr (LR >= 1) v = fmaxf(v, dppm<kDppQuadXor1>(v));
+    if constexpr (LR >= 2) v = fmaxf(v, dppm<kDppQuadXor2>(v));
+    if constexpr (LR >= 3) v = fmaxf(v, dppm<kDppRowHalfMirror>(v));
+    if constexpr (LR >= 4) v = fmaxf(v, dppm<kDppRowMirror>(v));
+    // rows not written by a broadcast keep their own value (max(v, v) = v)
+    if constexpr (LR >= 5) v = fmaxf(v, dppx<kDppRowBcast15, 0xA, false>(v, v));
+    if constexpr (LR >= 6) v = fmaxf(v, dppx<kDppRowBcast31, 0xC, false>(v, v));
+    if constexpr (LR == 5) {
+      const float a = rdlane(v, 31), b = rdlane(v, 63);
+      v = lane < 32u ? a : b;
+    }
+    if constexpr (LR == 6) v = rdlane(v, 63);
+    return v;
+  }
+  // inclusive prefix sum over the group (q = position in the group)
+  static __device__ __forceinline__ float scan(float v, uint32_t q) {
+    if constexpr (LR <= 3) {
+      // groups inside a row: row shifts and a position test
+      float o = dppx<0x111, 0xF, false>(0.f, v);
+      if (q >= 1u) v += o;
+      if constexpr (LR >= 2) {
+        o = dppx<0x112, 0xF, false>(0.f, v);
+        if (q >= 2u) v += o;
+      }
+      if constexpr (LR >= 3) {
+        o = dppx<0x114, 0xF, false>(0.f, v);
+        if (q >= 4u) v += o;
+      }
+    } else {
+      // groups of whole rows: lanes shifted in from outside the row read 0
+      v += dppx<0x111, 0xF, true>(0.f, v);
+      v += dppx<0x112, 0xF, true>(0.f, v);
+      v += dppx<0x114, 0xF, true>(0.f, v);
+      v += dppx<0x118, 0xF, true>(0.f, v);
+      if constexpr (LR >= 5) v += dppx<kDppRowBcast15, 0xA, false>(0.f, v);
+      if constexpr (LR >= 6) v += dppx<kDppRowBcast31, 0xC, false>(0.f, v);
+    }
+    return v;
+  }
+  static __device__ __forceinline__ float last(float v, uint32_t lane, uint32_t seg) {
+    if constexpr (LR == 6) return rdlane(v, 63);
+    if constexpr (LR == 5) {
+      const float a = rdlane(v, 31), b = rdlane(v, 63);
+      return lane < 32u ? a : b;
+    }
+    return bperm((seg + r - 1u) << 2, v);
+  }
+  static __device__ __forceinline__ float first(float v, uint32_t lane, uint32_t seg) {
+    if constexpr (LR == 6) return rdlane(v, 0);
+    if constexpr (LR == 5) {
+      const float a = rdlane(v, 0), b = rdlane(v, 32);
+      return lane < 32u ? a : b;
+    }
+    return bperm(seg << 2, v);
+  }
+  // first position p of the group with cdf_p > target, clamped to r - 1
+  static __device__ __forceinline__ uint32_t search(float cdf, float target, uint32_t seg) {
+    uint32_t pb = seg << 2;  // byte address of the candidate's lane
+#pragma unroll
+    for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
+      const float v = bperm(pb + ((s - 1u) << 2), cdf);
+      if (v <= target) pb += s << 2;
+    }
+    return (pb >> 2) - seg;
+  }
+};
+
+template <int LR> struct Grp<LR, double> {
+  static constexpr uint32_t r = 1u << LR;
+  static __device__ __forceinline__ double max(double v, uint32_t lane) { return seg_max(v, LR, lane); }
+  static __device__ __forceinline__ double scan(double v, uint32_t q) { return seg_scan(v, LR, q); }
+  static __device__ __forceinline__ double last(double v, uint32_t, uint32_t seg) {
+    return __shfl(v, (int)(seg + r - 1u), 64);
+  }
+  static __device__ __forceinline__ double first(double v, uint32_t, uint32_t seg) {
+    return __shfl(v, (int)seg, 64);
+  }
+  static __device__ __forceinline__ uint32_t search(double cdf, double target, uint32_t seg) {
+    uint32_t pos = 0;
+#pragma unroll
+    for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
+      const double v = __shfl(cdf, (int)(seg + pos + s - 1u), 64);
+      if (v <= target) pos += s;
+    }
+    return pos;
+  }
+};
+
+// Phase B of the wave path for r = 2^LR <= 64: a group is a segment of r
+// lanes; each wave handles 2 PPT tasks of 64 lanes, U of them interleaved.
+// Per group: max, scan of e^{l - max}, carried weight, the draw by binary
+// search of the scanned weights; positions overwrite the uniforms in LDS.
+template <int LR, typename T, int NT, int PPT>
+__device__ __forceinline__ void wave_groups(const T* scl, const T* scu, int* sca, T* colw, uint32_t P, T lnr,
+                                            bool sys, int wv, uint32_t lane, T& tile_lwmax) {
+  using G = Grp<LR, T>;
+  constexpr uint32_t r = 1u << LR;
+  constexpr int U = (2 * PPT) < 4 ? (2 * PPT) : 4;
+  const uint32_t seg = lane & ~(r - 1u);
+  const uint32_t q = lane & (r - 1u);
+#pragma unroll
+  for (int it = 0; it < (2 * PPT) / U; ++it) {
+    uint32_t c[U];
+    T l[U], m[U], cdf[U], tot[U], target[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t task = wv + (U * it + u) * (NT / 64);
+      c[u] = (task << (6 - LR)) + (lane >> LR);
+      l[u] = scl[c[u] * P + q];
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) m[u] = G::max(l[u], lane);
+#pragma unroll
+    for (int u = 0; u < U; ++u) cdf[u] = G::scan(fexp(l[u] - m[u]), q);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      tot[u] = G::last(cdf[u], lane, seg);
+      const T uu = scu[c[u] * P + q];
+      target[u] = sys ? ((T)q + G::first(uu, lane, seg)) * tot[u] / (T)r : uu * tot[u];
+    }
+    uint32_t pos[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) pos[u] = G::search(cdf[u], target[u], seg);
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      sca[c[u] * P + q] = (int)pos[u];
+      const T lw = m[u] + flog_ge1(tot[u]) - lnr;
+      tile_lwmax = fmaxT(tile_lwmax, lw);
+      if (q == 0) colw[c[u]] = lw;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Fused butterfly step (radix r < N) on one tile of r x C particles: the
 // body shared by the single-filter kernel and the batched kernel.
 // ---------------------------------------------------------------------------
@@ -685,48 +847,13 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   const bool sys = a.systematic != 0;
   T tile_lwmax = -INFINITY;
   if (!BLOCKPATH) {
-    // r <= 64: a group is a segment of r lanes; each wave handles 2 PPT
-    // tasks of 64 lanes, U of them interleaved at a time
-    constexpr int U = (2 * PPT) < 4 ? (2 * PPT) : 4;
-    const uint32_t seg = lane & ~(r - 1u);
-    const uint32_t q = lane & (r - 1u);
-#pragma unroll
-    for (int it = 0; it < (2 * PPT) / U; ++it) {
-      uint32_t c[U];
-      T l[U], m[U], cdf[U], tot[U], target[U];
-      uint32_t pos[U];
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        const uint32_t task = wv + (U * it + u) * (NT / 64);
-        c[u] = (task << (6 - log2r)) + (lane >> log2r);
-        l[u] = scl[c[u] * P + q];
-        pos[u] = 0u;
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) m[u] = seg_max(l[u], log2r, lane);
-#pragma unroll
-      for (int u = 0; u < U; ++u) cdf[u] = seg_scan(fexp(l[u] - m[u]), log2r, q);
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        tot[u] = __shfl(cdf[u], (int)(seg + r - 1u), 64);
-        const T uu = scu[c[u] * P + q];
-        const T u0 = __shfl(uu, (int)seg, 64);
-        target[u] = sys ? ((T)q + u0) * tot[u] / (T)r : uu * tot[u];
-      }
-      for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-          const T v = __shfl(cdf[u], (int)(seg + pos[u] + s - 1u), 64);
-          if (v <= target[u]) pos[u] += s;
-        }
-      }
-#pragma unroll
-      for (int u = 0; u < U; ++u) {
-        sca[c[u] * P + q] = (int)pos[u];
-        const T lw = m[u] + flog(tot[u]) - a.lnr;
-        tile_lwmax = fmaxT(tile_lwmax, lw);
-        if (q == 0) colw[c[u]] = lw;
-      }
+    switch (log2r) {
+      case 1: wave_groups<1, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
+      case 2: wave_groups<2, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
+      case 3: wave_groups<3, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
+      case 4: wave_groups<4, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
+      case 5: wave_groups<5, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
+      default: wave_groups<6, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
     }
   } else {
     // r > 64: 64-member chunks, chunk maxima and sums through LDS
@@ -762,7 +889,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const uint32_t qq = (ch << 6) + lane;
       scl[c * P + qq] += offs;
       if (ch == 0) {
-        const T lw = colm[c] + flog(tot) - a.lnr;
+        const T lw = colm[c] + flog_ge1(tot) - a.lnr;
         tile_lwmax = fmaxT(tile_lwmax, lw);
         if (lane == 0) {
           coltot[c] = tot;
