@@ -38,6 +38,7 @@ struct FilterHost {
 
 struct ClassHost {
   int D, mk, ppt;
+  int full = 1;  // every filter has d = D
   std::vector<uint32_t> filters;
   uint32_t nblocks = 0;
   size_t lds = 0;
@@ -235,13 +236,13 @@ pf_status batch_step(pf_batch* b, const float* y_dev, const uint8_t* active) {
   a.tcur = b->d_tcur;
   for (auto& c : b->classes) {
     a.block_filter = c.d_block_filter;
-    BatchReq rq{0, c.D, c.mk, c.ppt, c.nblocks, c.lds};
+    BatchReq rq{0, c.D, c.mk, c.ppt, c.full, c.nblocks, c.lds};
     hipError_t e = launch_batch(rq, a, b->stream);
     if (e != hipSuccess) return bhip(b, e, "batched step launch");
   }
   for (auto& c : b->classes) {
     a.class_filters = c.d_class_filters;
-    BatchReq rq{1, c.D, c.mk, c.ppt, (uint32_t)c.filters.size(), 0};
+    BatchReq rq{1, c.D, c.mk, c.ppt, c.full, (uint32_t)c.filters.size(), 0};
     hipError_t e = launch_batch(rq, a, b->stream);
     if (e != hipSuccess) return bhip(b, e, "batched finalize launch");
   }
@@ -422,6 +423,7 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
       b->classes.push_back(ch);
     }
     b->classes[cls_of[key]].filters.push_back(f);
+    if (F.d != F.D) b->classes[cls_of[key]].full = 0;
   }
   // default tile: two pairs per thread where every filter of the class has
   // at least 1024 particles

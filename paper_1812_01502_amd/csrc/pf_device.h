@@ -89,6 +89,8 @@ template <typename T> struct Single<bf16, T> {
 // Fast transcendental functions. FP32 uses the hardware exp2/log2/sqrt and the
 // revolution-scaled sin/cos; FP64 uses the device math library.
 // ---------------------------------------------------------------------------
+__device__ __forceinline__ float fmaT(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fmaT(double a, double b, double c) { return __builtin_fma(a, b, c); }
 __device__ __forceinline__ float fexp(float x) { return __expf(x); }
 __device__ __forceinline__ double fexp(double x) { return exp(x); }
 __device__ __forceinline__ float flog(float x) { return __logf(x); }
@@ -280,12 +282,14 @@ template <int D, typename T> struct Model<D, MK_LG_DIAG, T> {
     }
     return P->lconst - (T)0.5 * qf;
   }
-  // component j of f(xh, z): needs z[j] only
+  // component j of f(xh, z): needs z[j] only. Explicit FMAs: a sum of two
+  // products could otherwise be fused on either one, and two kernels holding
+  // this code could round differently.
   static __device__ __forceinline__ T row(const ModelParams<T>* __restrict__ P, const T (&xh)[D],
                                           const T (&z)[D], const int j) {
     T v = P->qd[j] * z[j];
 #pragma unroll
-    for (int k = 0; k < D; ++k) v += P->A[j * kMaxDim + k] * xh[k];
+    for (int k = 0; k < D; ++k) v = fmaT(P->A[j * kMaxDim + k], xh[k], v);
     return v;
   }
   static __device__ __forceinline__ void propagate(const ModelParams<T>* __restrict__ P,
@@ -307,7 +311,7 @@ template <int D, typename T> struct Model<D, MK_SV, T> {
   }
   static __device__ __forceinline__ T row(const ModelParams<T>* __restrict__ P, const T (&xh)[D],
                                           const T (&z)[D], const int) {
-    return P->phi * xh[0] + P->sigma * z[0];
+    return fmaT(P->phi, xh[0], P->sigma * z[0]);
   }
   static __device__ __forceinline__ void propagate(const ModelParams<T>* __restrict__ P,
                                                    const T (&xh)[D], const T (&z)[D], T (&xo)[D]) {

@@ -760,12 +760,14 @@ __device__ __forceinline__ void wave_groups(const T* scl, const T* scu, int* sca
 // Fused butterfly step (radix r < N) on one tile of r x C particles: the
 // body shared by the single-filter kernel and the batched kernel.
 // ---------------------------------------------------------------------------
-template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
+// FULL: the model dimension equals the compiled one (d = D), so every test
+// of a component index against d folds away.
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
 __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const uint32_t tile,
                                                unsigned char* smem) {
   constexpr int NLOC = 2 * PPT;
   constexpr int PS = partial_stride(D);
-  const int d = (int)a.d;
+  const int d = FULL ? D : (int)a.d;
   const uint32_t log2r = a.log2r, log2C = a.log2C;
   const uint32_t r = 1u << log2r, C = 1u << log2C;
   const uint32_t E = r << log2C;
@@ -980,11 +982,11 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 
 // Single filter: block b processes tile xcd_tile(b); block 0 also does the
 // step's bookkeeping.
-template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH>
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
 __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (blockIdx.x == 0) step_bookkeeping(a);
-  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH>(a, xcd_tile(blockIdx.x, a.ntiles), smem);
+  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH, FULL>(a, xcd_tile(blockIdx.x, a.ntiles), smem);
 }
 
 // ---------------------------------------------------------------------------
@@ -1023,7 +1025,7 @@ struct BatchArgs {
   uint32_t* tcur;                 // completed steps per filter
 };
 
-template <int D, int MK, int NT, int PPT>
+template <int D, int MK, int NT, int PPT, bool FULL>
 __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t f = ba.block_filter[blockIdx.x];
@@ -1059,7 +1061,7 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   a.k1 = F.k1;
   a.systematic = F.systematic;
   a.lnr = sg.lnr;
-  step_tile_body<D, MK, float, float, NT, PPT, false>(a, blockIdx.x - F.first_block, smem);
+  step_tile_body<D, MK, float, float, NT, PPT, false, FULL>(a, blockIdx.x - F.first_block, smem);
 }
 
 // Reduction of one filter's tile partials per block (after the class's

@@ -3,6 +3,7 @@
 
 namespace pfk {
 hipError_t launch_f32(const LaunchReq& rq, const void* args, hipStream_t st) {
+  if (rq.what == LW_STEP_TILE && rq.full) return launch_f32_full(rq, args, st);
   return launch_any<float, float>(rq, args, st);
 }
 }  // namespace pfk

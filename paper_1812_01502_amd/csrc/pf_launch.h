@@ -28,6 +28,7 @@ struct LaunchReq {
   int nt;        // threads per block
   int ppt;       // particle pairs per thread
   int blockpath; // tile kernels: 1 = r > 64
+  int full;      // tile kernels: d equals the compiled dimension
   uint32_t grid;
   size_t lds;    // dynamic LDS bytes
   uint32_t tile_elems;  // global draw: particles per weight tile
@@ -55,6 +56,75 @@ template <typename K> static hipError_t ensure_lds(K* kernel, size_t bytes) {
                              hipFuncAttributeMaxDynamicSharedMemorySize, (int)bytes);
 }
 
+// The fused step kernel for the request's tile shape.
+template <int D, int MK, typename T, typename S, bool FULL>
+static hipError_t launch_step_tile(const LaunchReq& rq, const StepArgs<T, S>& a, hipStream_t st) {
+  if (!rq.blockpath) {
+    if (rq.nt == 256 && rq.ppt == ppt_wave(D)) {
+      auto k = pf_step_tile<D, MK, T, S, 256, ppt_wave(D), false, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    if (rq.nt == 64 && rq.ppt == 1) {
+      auto k = pf_step_tile<D, MK, T, S, 64, 1, false, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(64), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    return hipErrorInvalidValue;
+  }
+  if (rq.nt == 256 && rq.ppt == ppt_block(D)) {
+    auto k = pf_step_tile<D, MK, T, S, 256, ppt_block(D), true, FULL>;
+    hipError_t e = ensure_lds(k, rq.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+    return hipGetLastError();
+  }
+  if constexpr (D <= 2) {
+    if (rq.nt == 256 && rq.ppt == 4) {
+      auto k = pf_step_tile<D, MK, T, S, 256, 4, true, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
+  }
+  if (rq.nt == 256 && rq.ppt == 1) {
+    auto k = pf_step_tile<D, MK, T, S, 256, 1, true, FULL>;
+    hipError_t e = ensure_lds(k, rq.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+    return hipGetLastError();
+  }
+  if (rq.nt == 1024 && rq.ppt == 1) {
+    auto k = pf_step_tile<D, MK, T, S, 1024, 1, true, FULL>;
+    hipError_t e = ensure_lds(k, rq.lds);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+    return hipGetLastError();
+  }
+  if constexpr (D <= 4) {
+    if (rq.nt == 1024 && rq.ppt == 2) {
+      auto k = pf_step_tile<D, MK, T, S, 1024, 2, true, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+      return hipGetLastError();
+    }
+    if (rq.nt == 1024 && rq.ppt == 4) {
+      auto k = pf_step_tile<D, MK, T, S, 1024, 4, true, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
+      return hipGetLastError();
+    }
+  }
+  return hipErrorInvalidValue;
+}
+
 template <int D, int MK, typename T, typename S>
 static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hipStream_t st) {
   switch (rq.what) {
@@ -62,72 +132,8 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       hipLaunchKernelGGL((pf_init_kernel<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
       return hipGetLastError();
     }
-    case LW_STEP_TILE: {
-      if (!rq.blockpath) {
-        if (rq.nt == 256 && rq.ppt == ppt_wave(D)) {
-          auto k = pf_step_tile<D, MK, T, S, 256, ppt_wave(D), false>;
-          hipError_t e = ensure_lds(k, rq.lds);
-          if (e != hipSuccess) return e;
-          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
-          return hipGetLastError();
-        }
-        if (rq.nt == 64 && rq.ppt == 1) {
-          auto k = pf_step_tile<D, MK, T, S, 64, 1, false>;
-          hipError_t e = ensure_lds(k, rq.lds);
-          if (e != hipSuccess) return e;
-          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(64), rq.lds, st, a);
-          return hipGetLastError();
-        }
-        return hipErrorInvalidValue;
-      }
-      if (rq.nt == 256 && rq.ppt == ppt_block(D)) {
-        auto k = pf_step_tile<D, MK, T, S, 256, ppt_block(D), true>;
-        hipError_t e = ensure_lds(k, rq.lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
-        return hipGetLastError();
-      }
-      if constexpr (D <= 2) {
-        if (rq.nt == 256 && rq.ppt == 4) {
-          auto k = pf_step_tile<D, MK, T, S, 256, 4, true>;
-          hipError_t e = ensure_lds(k, rq.lds);
-          if (e != hipSuccess) return e;
-          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
-          return hipGetLastError();
-        }
-      }
-      if (rq.nt == 256 && rq.ppt == 1) {
-        auto k = pf_step_tile<D, MK, T, S, 256, 1, true>;
-        hipError_t e = ensure_lds(k, rq.lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
-        return hipGetLastError();
-      }
-      if (rq.nt == 1024 && rq.ppt == 1) {
-        auto k = pf_step_tile<D, MK, T, S, 1024, 1, true>;
-        hipError_t e = ensure_lds(k, rq.lds);
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
-        return hipGetLastError();
-      }
-      if constexpr (D <= 4) {
-        if (rq.nt == 1024 && rq.ppt == 2) {
-          auto k = pf_step_tile<D, MK, T, S, 1024, 2, true>;
-          hipError_t e = ensure_lds(k, rq.lds);
-          if (e != hipSuccess) return e;
-          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
-          return hipGetLastError();
-        }
-        if (rq.nt == 1024 && rq.ppt == 4) {
-          auto k = pf_step_tile<D, MK, T, S, 1024, 4, true>;
-          hipError_t e = ensure_lds(k, rq.lds);
-          if (e != hipSuccess) return e;
-          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
-          return hipGetLastError();
-        }
-      }
-      return hipErrorInvalidValue;
-    }
+    case LW_STEP_TILE:
+      return launch_step_tile<D, MK, T, S, false>(rq, a, st);
     case LW_GLOBAL_WEIGHT: {
       if (rq.nt == 256 && rq.ppt == ppt_gweight(D)) {
         hipLaunchKernelGGL((pf_global_weight<D, MK, T, S, 256, ppt_gweight(D)>), dim3(rq.grid),
@@ -198,6 +204,7 @@ static hipError_t launch_any(const LaunchReq& rq, const void* args, hipStream_t 
 struct BatchReq {
   int finalize;  // 0: step tiles, 1: reductions
   int D, mk, ppt;
+  int full;      // every filter of the class has d = D
   uint32_t grid;
   size_t lds;
 };
@@ -205,14 +212,10 @@ constexpr int kBatchNT = 256;
 // Pairs per thread of the batched tiles (E = 512 PPT particles per tile).
 constexpr bool batch_ppt_ok(int D, int ppt) { return ppt == 1 || (ppt == 2 && D <= 8); }
 
-template <int D, int MK>
-static hipError_t launch_batch_model(const BatchReq& rq, const BatchArgs& a, hipStream_t st) {
-  if (rq.finalize) {
-    hipLaunchKernelGGL((pf_batch_finalize<D, kBatchNT>), dim3(rq.grid), dim3(kBatchNT), 0, st, a);
-    return hipGetLastError();
-  }
+template <int D, int MK, bool FULL>
+static hipError_t launch_batch_tiles(const BatchReq& rq, const BatchArgs& a, hipStream_t st) {
   if (rq.ppt == 1) {
-    auto k = pf_batch_tile<D, MK, kBatchNT, 1>;
+    auto k = pf_batch_tile<D, MK, kBatchNT, 1, FULL>;
     hipError_t e = ensure_lds(k, rq.lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kBatchNT), rq.lds, st, a);
@@ -220,7 +223,7 @@ static hipError_t launch_batch_model(const BatchReq& rq, const BatchArgs& a, hip
   }
   if constexpr (D <= 8) {
     if (rq.ppt == 2) {
-      auto k = pf_batch_tile<D, MK, kBatchNT, 2>;
+      auto k = pf_batch_tile<D, MK, kBatchNT, 2, FULL>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kBatchNT), rq.lds, st, a);
@@ -230,7 +233,37 @@ static hipError_t launch_batch_model(const BatchReq& rq, const BatchArgs& a, hip
   return hipErrorInvalidValue;
 }
 
+template <int D, int MK>
+static hipError_t launch_batch_model(const BatchReq& rq, const BatchArgs& a, hipStream_t st) {
+  if (rq.finalize) {
+    hipLaunchKernelGGL((pf_batch_finalize<D, kBatchNT>), dim3(rq.grid), dim3(kBatchNT), 0, st, a);
+    return hipGetLastError();
+  }
+  return rq.full ? launch_batch_tiles<D, MK, true>(rq, a, st) : launch_batch_tiles<D, MK, false>(rq, a, st);
+}
+
 hipError_t launch_batch(const BatchReq& rq, const BatchArgs& a, hipStream_t st);
+
+// Step-tile launches with d = D (instantiated in their own translation unit).
+template <typename T, typename S>
+static hipError_t launch_full_any(const LaunchReq& rq, const void* args, hipStream_t st) {
+  const StepArgs<T, S>& a = *reinterpret_cast<const StepArgs<T, S>*>(args);
+  if (rq.mk == MK_SV) return rq.D == 1 ? launch_step_tile<1, MK_SV, T, S, true>(rq, a, st) : hipErrorInvalidValue;
+#define PFK_FULL_DIMS(MKV)                                                   \
+  switch (rq.D) {                                                            \
+    case 1: return launch_step_tile<1, MKV, T, S, true>(rq, a, st);          \
+    case 2: return launch_step_tile<2, MKV, T, S, true>(rq, a, st);          \
+    case 4: return launch_step_tile<4, MKV, T, S, true>(rq, a, st);          \
+    case 8: return launch_step_tile<8, MKV, T, S, true>(rq, a, st);          \
+    case 16: return launch_step_tile<16, MKV, T, S, true>(rq, a, st);        \
+    default: return hipErrorInvalidValue;                                    \
+  }
+  if (rq.mk == MK_LG_DENSE) { PFK_FULL_DIMS(MK_LG_DENSE) }
+  if (rq.mk == MK_LG_DIAG) { PFK_FULL_DIMS(MK_LG_DIAG) }
+#undef PFK_FULL_DIMS
+  return hipErrorInvalidValue;
+}
+hipError_t launch_f32_full(const LaunchReq& rq, const void* args, hipStream_t st);
 
 // Entry points of the three dtype translation units.
 hipError_t launch_f32(const LaunchReq& rq, const void* args, hipStream_t st);

@@ -193,6 +193,7 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.nt = sp.nt;
     rq.ppt = sp.ppt;
     rq.blockpath = sp.blockpath;
+    rq.full = h->d == h->D ? 1 : 0;
     rq.grid = sp.ntiles;
     rq.lds = sp.lds;
     e = launch(h, rq, &a);
