@@ -21,21 +21,27 @@ from .butterfly import group_resample
 from .plan import interaction_matrix, place_values
 
 
-def augmented_resample(log_g: np.ndarray, uniforms, plan, resampler="multinomial"):
+def augmented_resample(log_g: np.ndarray, uniforms, plan, resampler="multinomial",
+                       detail: bool = False):
     """Run all stages of ``plan`` on input log-weights ``log_g``.
 
     ``uniforms[k]`` holds the destination uniforms of stage ``k``. Returns
     ``(origin, log V_S)``: ``origin[i]`` is the input particle that final
-    particle ``i`` copies.
+    particle ``i`` copies. With ``detail`` a third item lists, per stage,
+    ``(ancestors, margins)`` of that stage's draws (see ``group_resample``).
     """
     N = log_g.shape[0]
     R = place_values(plan)
     origin = np.arange(N)
     lv = np.asarray(log_g, dtype=np.float64)
+    stages = []
     for k, r in enumerate(plan):
-        anc, lv_new, _ = group_resample(lv, uniforms[k], r, R[k], resampler)
+        anc, lv_new, margin = group_resample(lv, uniforms[k], r, R[k], resampler)
         origin = origin[anc]
         lv = lv_new
+        stages.append((anc, margin))
+    if detail:
+        return origin, lv, stages
     return origin, lv
 
 

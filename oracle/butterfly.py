@@ -18,6 +18,8 @@ What one time step computes (the steps in the paper's order):
   incoming log-weight of the next step.
 * ``r >= N`` is one stage whose group is the whole population:
   Algorithm 2 (multinomial resampling) of the plain bootstrap filter.
+* ``full_cycle``: every step runs all ``S`` stages of Algorithm 3 instead of
+  one (``_step_full``).
 
 Step ``t`` in detail (log domain, FP64):
 
@@ -143,7 +145,10 @@ class ButterflyOracle:
     """Butterfly particle filter, one rotating stage per step (FP64)."""
 
     def __init__(self, model, N: int, radix: int, resampler: str = MULTINOMIAL,
-                 seed: int = 0, stream_id: int = 0):
+                 seed: int = 0, stream_id: int = 0, full_cycle: bool = False):
+        """``full_cycle``: every time step runs all ``S`` stages (Algorithm 3
+        in full) instead of the one rotating stage ``k = t mod S``."""
+        self.full_cycle = bool(full_cycle)
         self.model = model
         self.N = int(N)
         self.radix = int(radix)
@@ -167,6 +172,8 @@ class ButterflyOracle:
     def step(self, st: State, y, keep=True):
         """Advance one time step with observation ``y``; returns
         ``(new_state, record)``."""
+        if self.full_cycle:
+            return self._step_full(st, y, keep)
         t = st.t
         k = t % self.S
         r, R = self.plan[k], self.R[k]
@@ -189,6 +196,32 @@ class ButterflyOracle:
                    max_ell=est["max_ell"], offset=float(c))
         if keep:
             rec.update(ancestors=anc, margin=margin, logw_new=new_lw, ell=ell, draw=info)
+        return State(x=x, logw=logw, t=t + 1, log_norm=log_norm), rec
+
+    def _step_full(self, st: State, y, keep):
+        """One time step with all S stages (Algorithm 3): weight with
+        ``y_t``, estimate, resample through stages 0..S-1 carrying the group
+        means (after the last stage every weight is the global mean, Lemma
+        3(c)), gather, propagate. Stage ``s`` draws the uniforms of
+        ``philox.stage_uniforms``."""
+        from .augmented import augmented_resample
+        t = st.t
+        tau = t + 1
+        ell = st.logw + models.log_g(self.model, st.x, y)
+        est = weighted_estimate(st.x, ell, st.logw)
+        U = [philox.stage_uniforms(self.seed, self.stream_id, tau, self.N, k) for k in range(self.S)]
+        origin, lv, stages = augmented_resample(ell, U, self.plan, self.resampler, detail=True)
+        xhat = st.x[origin]
+        c = np.max(lv)
+        logw = lv - c
+        z = philox.normals(self.seed, self.stream_id, tau, self.N, self.model.d)
+        x = models.propagate(self.model, xhat, z)
+        log_norm = st.log_norm + est["dlog"]
+        rec = dict(t=t, stage=self.S, radix=self.radix, stride=1, mean=est["mean"],
+                   var=est["var"], ess=est["ess"], log_norm=log_norm,
+                   max_ell=est["max_ell"], offset=float(c))
+        if keep:
+            rec.update(origin=origin, stages=stages, ell=ell)
         return State(x=x, logw=logw, t=t + 1, log_norm=log_norm), rec
 
     def run(self, ys, keep=False, state: State | None = None):

@@ -157,3 +157,44 @@ def test_augmented_sampler_matches_exact_law():
     for i in range(N):
         emp[i] = np.bincount(src[:, i], minlength=N) / reps
     assert np.max(np.abs(emp - law)) < 5 * np.sqrt(0.25 / reps)
+
+
+def test_stage_uniforms_are_distinct_streams():
+    """Stage 0 of a multi-stage step uses the step's ordinary uniforms; every
+    later stage draws from its own block, on the same 24-bit grid."""
+    u0 = philox.stage_uniforms(3, 1, 7, 64, 0)
+    assert np.array_equal(u0, philox.resample_uniforms(3, 1, 7, 64))
+    us = [philox.stage_uniforms(3, 1, 7, 64, s) for s in range(4)]
+    for a in range(4):
+        assert np.all((us[a] * 2 ** 24) == np.floor(us[a] * 2 ** 24))
+        for b in range(a):
+            assert not np.array_equal(us[a], us[b])
+
+
+@pytest.mark.parametrize("N,r", [(8, 2), (16, 4), (64, 4), (1 << 10, 32)])
+def test_full_cycle_step_leaves_equal_weights_and_unbiased_counts(N, r):
+    """One full-cycle step of the filter oracle: after all S stages every
+    log-weight is the log of the global mean (Lemma 3(c)); over many seeds
+    the copies of each input particle average N g_j / sum g (Proposition 1)."""
+    import workloads as W
+    from oracle import ButterflyOracle, State
+    model = W.ar1_model()
+    rng = np.random.Generator(np.random.PCG64(N + r))
+    x0 = rng.standard_normal((N, 1))
+    lw0 = rng.standard_normal(N) * 0.3
+    st = State(x=x0, logw=lw0 - lw0.max(), t=4, log_norm=0.0)
+    y = np.array([0.4])
+    orc = ButterflyOracle(model, N, r, seed=0, full_cycle=True)
+    _, rec = orc.step(st, y, keep=True)
+    ell = rec["ell"]
+    reps = 400 if N <= 64 else 40
+    counts = np.zeros(N)
+    for sd in range(reps):
+        o = ButterflyOracle(model, N, r, seed=sd, full_cycle=True)
+        st1, rr = o.step(st, y, keep=True)
+        assert np.max(np.abs(st1.logw)) < 1e-12       # all weights equal
+        counts += np.bincount(rr["origin"], minlength=N)
+    g = np.exp(ell - ell.max())
+    expect = N * g / g.sum()
+    sd_ = np.sqrt(np.maximum(expect, 1e-3) / reps)
+    assert np.all(np.abs(counts / reps - expect) <= 6 * sd_ + 1e-9)
