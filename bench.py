@@ -256,9 +256,9 @@ def main():
     yd = torch.tensor(ys, dtype=torch.float32, device="cuda").contiguous()
     stream = torch.cuda.current_stream()
 
-    def make(radix):
+    def make(radix, full_cycle=False):
         return P.Filter(model, N, radix, seed=cfg["seed_pf"], history=4,
-                        stream=stream.cuda_stream)
+                        stream=stream.cuda_stream, full_cycle=full_cycle)
 
     if args.mode == "profile":
         # step kernels only (for rocprofv3), then a plain copy of known size
@@ -313,6 +313,16 @@ def main():
     per_radix[str(args.radix)] = dict(particle_steps_per_s=value, ms_per_step=ms_step,
                                       hbm_frac=achieved / HBM_PEAK_GBS, stages=plan)
 
+    # -- full augmented resampling per step (all S stages, Algorithm 3) ----------
+    fc = make(args.radix, full_cycle=True)
+    fc.run(yd.data_ptr(), Wm, d)
+    fwall, fev = timed_run(fc, yd[Wm:], K, d)
+    S = len(plan)
+    fc.close()
+    full_cycle = {"stages_per_step": S, "particle_steps_per_s": N * K / fwall, "ms_per_step": fwall / K * 1e3,
+                  "bytes_per_particle_step": S * B,
+                  "hbm_frac_algorithmic": S * B * N / (fev / K) / 1e9 / HBM_PEAK_GBS}
+
     out = {
         "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
         "value": value,
@@ -342,6 +352,7 @@ def main():
                        "hbm_frac_algorithmic": Bg * N / (gev / K) / 1e9 / HBM_PEAK_GBS,
                        "latency_us": {"p50": gp50, "p99": gp99}},
         "per_radix": per_radix,
+        "full_cycle": full_cycle,
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
     }
     if not args.no_batch and args.mode == "bench":

@@ -98,15 +98,19 @@ typedef struct {
   uint32_t stream_id;    /* Philox counter word 3 (identity of the filter) */
   uint32_t history;      /* per-step estimate records kept on device (0 -> 1) */
   uint32_t keep_ancestors; /* nonzero: record each step's ancestor indices */
-  uint32_t reserved;
+  uint32_t full_cycle;     /* nonzero: every time step runs all S stages of
+                              Algorithm 3 (full augmented resampling; the
+                              output is unweighted, Lemma 3(c)); zero: one
+                              stage per step, k = t mod S */
 } pf_config;
 
 /* Estimate of one completed step t (the weighted cloud
  * before resampling, i.e. the filtering law of x_t given y_0..y_t). */
 typedef struct {
   uint32_t t;              /* step index the record belongs to */
-  uint32_t stage;          /* butterfly stage k = t mod S used by the step */
-  uint32_t radix;          /* radix r_k of that stage */
+  uint32_t stage;          /* butterfly stage k = t mod S used by the step
+                              (S: a full-cycle step ran every stage) */
+  uint32_t radix;          /* radix r_k of that stage (full cycle: the radix) */
   uint32_t valid;          /* 1 if the step has run */
   double log_normaliser;   /* running log p-hat(y_0..y_t), FP64 */
   double ess;              /* (sum w)^2 / (N sum w^2), in [1/N, 1] */
@@ -199,7 +203,8 @@ pf_status pf_load(pf_handle* h, const void* buf, uint64_t len);
 
 /* Ancestor index a(i) (into the previous cloud) of every particle of the
  * last step (host output, N uint32; synchronises). Requires
- * cfg.keep_ancestors, else PF_E_STATE. */
+ * cfg.keep_ancestors, else PF_E_STATE. In full-cycle mode: the ancestors of
+ * the last stage (into the cloud after the previous stage). */
 pf_status pf_get_ancestors(pf_handle* h, uint32_t* anc_host);
 
 /* Sizes and plan of the handle (host output). */

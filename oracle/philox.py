@@ -24,7 +24,8 @@ Stream mapping (one call serves the particle pair ``(2p, 2p+1)``):
   give dimension ``2b`` with the same cosine/sine split.
 * when one time step runs several resampling stages (all ``S`` stages of
   Algorithm 3), stage ``s >= 1`` takes its uniforms from words ``w0, w1`` of
-  block ``STAGE_BLOCK + s``; stage 0 uses block 0 as above.
+  block 0 at counter word ``tau + s 2^24`` (``tau < 2^24``); stage 0 uses the
+  step's own uniforms.
 * Box-Muller (Box and Muller, 1958) on words ``(wa, wb)``:
   ``u1 = ((wa >> 8) + 1) 2^-24`` in ``(0, 1]``, ``u2 = (wb >> 8) 2^-24``,
   ``rho = sqrt(-2 ln u1)``, normals ``rho cos(2 pi u2)``, ``rho sin(2 pi u2)``.
@@ -42,7 +43,7 @@ W0 = 0x9E3779B9
 W1 = 0xBB67AE85
 MASK32 = 0xFFFFFFFF
 TWO_M24 = 2.0 ** -24
-STAGE_BLOCK = 0x100   # uniforms of stage s >= 1 of a multi-stage step
+STAGE_TAU = 1 << 24   # uniforms of stage s >= 1 of a multi-stage step: tau + s STAGE_TAU
 
 
 def philox4x32_10(c0, c1, c2, c3, k0, k1):
@@ -117,15 +118,9 @@ def resample_uniforms(seed: int, stream_id: int, tau: int, n: int) -> np.ndarray
 def stage_uniforms(seed: int, stream_id: int, tau: int, n: int, stage: int) -> np.ndarray:
     """Destination uniforms of resampling stage ``stage`` of a multi-stage
     step (stage 0: the step's ordinary uniforms)."""
-    if stage == 0:
-        return resample_uniforms(seed, stream_id, tau, n)
-    if n % 2:
-        raise ValueError("the particle count must be even")
-    w0, w1, _, _ = _pair_words(seed, stream_id, tau, n // 2, STAGE_BLOCK + stage)
-    u = np.empty(n)
-    u[0::2] = word_to_uniform(w0)
-    u[1::2] = word_to_uniform(w1)
-    return u
+    if tau >= STAGE_TAU or not 0 <= stage < 256:
+        raise ValueError("multi-stage steps need tau < 2^24 and fewer than 256 stages")
+    return resample_uniforms(seed, stream_id, tau + stage * STAGE_TAU, n)
 
 
 def normals(seed: int, stream_id: int, tau: int, n: int, d: int) -> np.ndarray:

@@ -77,7 +77,7 @@ class Filter:
 
     def __init__(self, model, n: int, radix: int, resampler: str = "multinomial",
                  dtype: str = "f32", seed: int = 0, stream_id: int = 0, history: int = 1,
-                 keep_ancestors: bool = False, stream: int | None = None):
+                 keep_ancestors: bool = False, stream: int | None = None, full_cycle: bool = False):
         self._lib = L.load()
         self.d = int(model.d)
         self.n = int(n)
@@ -93,6 +93,7 @@ class Filter:
         c.stream_id = int(stream_id)
         c.history = int(history)
         c.keep_ancestors = 1 if keep_ancestors else 0
+        c.full_cycle = 1 if full_cycle else 0
         h = ctypes.c_void_p()
         st = self._lib.pf_create(ctypes.byref(m), ctypes.byref(c),
                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))

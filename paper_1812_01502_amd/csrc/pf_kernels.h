@@ -24,6 +24,16 @@
 
 namespace pfk {
 
+// What a launch of the step kernel does besides resampling: weight with the
+// observation (and write the estimate partials), and propagate. A full-cycle
+// time step runs every stage: only the first weights, only the last
+// propagates.
+constexpr uint32_t kStepWeight = 1u;
+constexpr uint32_t kStepPropagate = 2u;
+// Uniforms of stage s >= 1 of a full-cycle step come from block 0 of
+// counter word tau + s kStageTau (tau = t + 1 < kStageTau).
+constexpr uint32_t kStageTau = 1u << 24;
+
 template <typename T, typename S> struct StepArgs {
   const S* x_in;
   S* x_out;
@@ -41,6 +51,9 @@ template <typename T, typename S> struct StepArgs {
   uint64_t N;
   uint32_t log2r, log2R, log2C, pad;  // stage radix, stride, tile columns, LDS row pad
   uint32_t t, k;
+  uint32_t u;                // offset-slot index: steps, or stages of full-cycle steps
+  uint32_t flags;            // kStepWeight | kStepPropagate
+  uint32_t utau;             // counter word of the resampling uniforms (t + 1, or a stage's)
   uint32_t ntiles;
   uint32_t radix;            // r_k (N on the global path)
   uint32_t k0, k1, sid;
@@ -151,6 +164,7 @@ struct FinArgs {
   // record (a later step owns its history slot); the next offset comes from
   // the following step's bookkeeping (use_step_off) or from the slots
   uint32_t multi, slot, write_rec, use_step_off;
+  uint32_t unext;  // offset-slot index of the next step (its offset is this step's next offset)
 };
 
 // FP64 reduction of one step's tile partials by one block, in a fixed order.
@@ -184,9 +198,9 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
   double offv = -INFINITY, ln0 = 0.0;
   if (wv == 0) {
     if (f.use_step_off) {
-      if (lane == 0) offv = f.ctl->step_off[(f.t + 1) % kMaxPending];
+      if (lane == 0) offv = f.ctl->step_off[f.unext % kMaxPending];
     } else if (lane < kOffSlots) {
-      offv = ord_decode(*off_slot(f.ctl, f.t + 1, lane));
+      offv = ord_decode(*off_slot(f.ctl, f.unext, lane));
     }
     if (lane == 0 && !f.multi) ln0 = f.ctl->log_norm;
   }
@@ -326,7 +340,7 @@ __global__ void __launch_bounds__(NT) pf_finalize_kernel(FinArgs f, const T* par
 // partials in ring slot t mod fm.ring); a second launch adds the running
 // log-normaliser in step order.
 struct FinStep {
-  uint32_t t, k, radix, ntiles;
+  uint32_t t, k, radix, ntiles, unext;
 };
 struct FinMulti {
   Ctl* ctl;
@@ -356,6 +370,7 @@ __global__ void __launch_bounds__(NT) pf_finalize_multi(FinMulti fm) {
   f.slot = i;
   f.write_rec = (fm.n - 1u - i) < fm.hist_cap ? 1u : 0u;
   f.use_step_off = (i + 1u < fm.n) ? 1u : 0u;
+  f.unext = st.unext;
   const T* part = reinterpret_cast<const T*>(fm.part_base) + (size_t)(st.t % fm.ring) * fm.part_stride;
   finalize_partials<D, T, NT, fin_batch<D, T>()>(f, part, st.ntiles, red);
 }
@@ -378,10 +393,10 @@ __global__ void __launch_bounds__(64) pf_finalize_prefix(FinMulti fm) {
 template <typename T, typename S>
 __device__ __forceinline__ void step_bookkeeping(const StepArgs<T, S>& a) {
   if (threadIdx.x < 64u) {
-    const double o = read_offset(a.ctl, a.t);
-    if (threadIdx.x == 0) a.ctl->step_off[a.t % kMaxPending] = o;
+    const double o = read_offset(a.ctl, a.u);
+    if (threadIdx.x == 0) a.ctl->step_off[a.u % kMaxPending] = o;
   }
-  clear_offset(a.ctl, a.t + 2, -INFINITY);
+  clear_offset(a.ctl, a.u + 2, -INFINITY);
 }
 
 // Partial sums of one tile from per-thread register values (relative to the
@@ -792,7 +807,9 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 
   const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
   const uint64_t N = a.N;
-  const T off = (T)read_offset(a.ctl, a.t);
+  const T off = (T)read_offset(a.ctl, a.u);
+  const bool weight = (a.flags & kStepWeight) != 0u;
+  const bool prop = (a.flags & kStepPropagate) != 0u;
   T y[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) y[j] = (j < d) ? (a.y_dev ? a.y_dev[j] : a.y_val[j]) : (T)0;
@@ -816,15 +833,18 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     }
     Pair<T, T>::load(a.lw_in + ga[it], lwn[2 * it], lwn[2 * it + 1]);
   }
+  // block 0 of counter word utau: the step's own (utau = tau) or, for a
+  // later stage of a full-cycle step, the stage's (utau = tau + s 2^24),
+  // whose dimension-0 normals are not used (phase C draws the step's)
 #pragma unroll
   for (int it = 0; it < PPT; ++it)
-    pair_block0<T>((uint32_t)(ga[it] >> 1), tau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
+    pair_block0<T>((uint32_t)(ga[it] >> 1), a.utau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
                    z0r[2 * it], z0r[2 * it + 1]);
   T tmax = -INFINITY;
 #pragma unroll
   for (int e = 0; e < NLOC; ++e) {
     lwn[e] -= off;
-    lr[e] = lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y);
+    lr[e] = weight ? lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y) : lwn[e];
     tmax = fmaxT(tmax, lr[e]);
 #pragma unroll
     for (int j = 0; j < D; ++j)
@@ -832,17 +852,19 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     scl[ca[e] * P + qa[e]] = lr[e];
     scu[ca[e] * P + qa[e]] = ur[e];
   }
-  // tile reference point for the variance sums: the tile's first particle
-  if (tid == 0) {
+  if (weight) {
+    // tile reference point for the variance sums: the tile's first particle
+    if (tid == 0) {
 #pragma unroll
-    for (int j = 0; j < D; ++j) shx[j] = xr[0][j];
+      for (int j = 0; j < D; ++j) shx[j] = xr[0][j];
+    }
+    const T mtile = block_max<T, NT>(tmax, red);  // (its barriers publish shx)
+    T sh[D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) sh[j] = shx[j];
+    T* prt = a.part_out + (size_t)tile * PS;
+    tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
   }
-  const T mtile = block_max<T, NT>(tmax, red);  // (its barriers publish shx)
-  T sh[D];
-#pragma unroll
-  for (int j = 0; j < D; ++j) sh[j] = shx[j];
-  T* prt = a.part_out + (size_t)tile * PS;
-  tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
   __syncthreads();
 
   // ---- phase B: group max / scan / carried weight / draw -------------------
@@ -922,7 +944,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     T mx = shx[0];
 #pragma unroll
     for (int w = 1; w < NT / 64; ++w) mx = fmaxT(mx, shx[w]);
-    __hip_atomic_fetch_max(off_slot(a.ctl, a.t + 1, tile % kOffSlots), ord_encode((double)mx),
+    __hip_atomic_fetch_max(off_slot(a.ctl, a.u + 1, tile % kOffSlots), ord_encode((double)mx),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   }
 
@@ -956,8 +978,19 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       a.anc[g0] = ai[0];
       a.anc[g0 + 1] = ai[1];
     }
+    if (!prop) {
+      // an inner stage of a full-cycle step: the gathered states as they are
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + g0, xh[0][j], xh[1][j]);
+      continue;
+    }
     z[0][0] = z0r[2 * it];
     z[1][0] = z0r[2 * it + 1];
+    if (a.utau != tau) {
+      const Words w0 = philox((uint32_t)(g0 >> 1), tau, 0u, a.sid, a.k0, a.k1);
+      box_muller(w0.w2, w0.w3, z[0][0], z[1][0]);
+    }
     Pair<S, T>::store(a.x_out + g0, Model<D, MK, T>::row(a.mp, xh[0], z[0], 0),
                       Model<D, MK, T>::row(a.mp, xh[1], z[1], 0));
     const uint32_t pr = (uint32_t)(g0 >> 1);
@@ -1054,6 +1087,9 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   a.pad = sg.pad;
   a.t = t;
   a.k = k;
+  a.u = t;
+  a.flags = kStepWeight | kStepPropagate;
+  a.utau = t + 1u;
   a.ntiles = F.ntiles;
   a.radix = 1u << sg.log2r;
   a.sid = F.sid;
@@ -1087,6 +1123,7 @@ __global__ void __launch_bounds__(NT) pf_batch_finalize(BatchArgs ba) {
   fa.slot = 0u;
   fa.write_rec = 1u;
   fa.use_step_off = 0u;
+  fa.unext = t + 1u;
   finalize_partials<D, float, NT, fin_batch<D, float>()>(fa, F.part, F.ntiles, red);
   if (threadIdx.x < 64u) {
     clear_offset(F.ctl, t + 2u, -INFINITY);
@@ -1127,7 +1164,7 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     if (a.lw_nonzero) {
       T w0, w1;
       Pair<T, T>::load(a.lw_in + base + e, w0, w1);
-      const T off = (T)read_offset(a.ctl, a.t);
+      const T off = (T)read_offset(a.ctl, a.u);
       lwn[e] = w0 - off;
       lwn[e + 1] = w1 - off;
     }
@@ -1215,7 +1252,7 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     run += a.gscale[b] * (double)part[(size_t)b * PS + 1];
   }
   if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
-  if (tid == 0) *off_slot(a.ctl, a.t + 1, 0) = ord_encode(0.0);
+  if (tid == 0) *off_slot(a.ctl, a.u + 1, 0) = ord_encode(0.0);
   step_bookkeeping(a);
 }
 

@@ -52,6 +52,8 @@ struct pf_handle {
   double* gscale = nullptr;
   uint32_t g_tile = 0, g_ntiles = 0, g_nt = 256, g_ppt = 1;
   uint64_t t = 0;
+  uint64_t u = 0;            // offset-slot index: one per kernel launch of the tile path
+  bool full_cycle = false;   // every step runs all S stages
   uint64_t model_hash = 0;   // FNV-1a of the model parameters (checkpoint check)
   bool lw_zero = true;       // every log-weight is 0 (global path bookkeeping)
   uint64_t bytes = 0;
@@ -155,6 +157,7 @@ pf_status run_init(pf_handle* h) {
   hipError_t e = launch(h, rq, &a);
   if (e != hipSuccess) return hip_fail(h, e, "init kernel launch");
   h->t = 0;
+  h->u = 0;
   h->lw_zero = true;
   h->pending.clear();
   return PF_OK;
@@ -162,9 +165,11 @@ pf_status run_init(pf_handle* h) {
 
 pf_status flush(pf_handle* h);
 
-// One time step; y either by value (y_host) or in device memory (y_dev).
+// One launch of the fused tile kernel for stage k with the given flags.
 template <typename T, typename S>
-pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
+pf_status launch_stage(pf_handle* h, const double* y_host, const void* y_dev, uint32_t k, uint32_t flags,
+                       uint32_t utau) {
+  const StagePlan& sp = h->stages[k];
   StepArgs<T, S> a;
   fill_common<T, S>(h, a);
   if (y_dev) {
@@ -172,33 +177,61 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
   } else {
     for (int j = 0; j < h->d; ++j) a.y_val[j] = (T)y_host[j];
   }
-  const uint32_t S_ = (uint32_t)h->stages.size();
-  const uint32_t k = (uint32_t)(h->t % S_);
-  const StagePlan& sp = h->stages[k];
   a.t = (uint32_t)h->t;
   a.k = k;
+  a.u = (uint32_t)h->u;
+  a.flags = flags;
+  a.utau = utau;
   a.radix = sp.r;
   a.log2r = sp.log2r;
   a.log2R = sp.log2R;
   a.lnr = (T)std::log((double)sp.r);
-  hipError_t e;
-  if (!h->global) {
-    a.log2C = sp.log2C;
-    a.pad = sp.pad;
-    a.ntiles = sp.ntiles;
-    LaunchReq rq{};
-    rq.what = LW_STEP_TILE;
-    rq.D = h->D;
-    rq.mk = h->mk;
-    rq.nt = sp.nt;
-    rq.ppt = sp.ppt;
-    rq.blockpath = sp.blockpath;
-    rq.full = h->d == h->D ? 1 : 0;
-    rq.grid = sp.ntiles;
-    rq.lds = sp.lds;
-    e = launch(h, rq, &a);
-    if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
-  } else {
+  a.log2C = sp.log2C;
+  a.pad = sp.pad;
+  a.ntiles = sp.ntiles;
+  LaunchReq rq{};
+  rq.what = LW_STEP_TILE;
+  rq.D = h->D;
+  rq.mk = h->mk;
+  rq.nt = sp.nt;
+  rq.ppt = sp.ppt;
+  rq.blockpath = sp.blockpath;
+  rq.full = h->d == h->D ? 1 : 0;
+  rq.grid = sp.ntiles;
+  rq.lds = sp.lds;
+  hipError_t e = launch(h, rq, &a);
+  if (e != hipSuccess) return hip_fail(h, e, "step kernel launch");
+  h->cur ^= 1;
+  h->u += 1;
+  return PF_OK;
+}
+
+// One time step; y either by value (y_host) or in device memory (y_dev).
+// Rotating mode: stage k = t mod S. Full-cycle mode: stages 0..S-1 in one
+// step (only the first weights, only the last propagates).
+template <typename T, typename S>
+pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
+  const uint32_t S_ = (uint32_t)h->stages.size();
+  FinStep fs;
+  fs.t = (uint32_t)h->t;
+  if (h->global) {
+    const uint32_t k = 0;
+    const StagePlan& sp = h->stages[k];
+    StepArgs<T, S> a;
+    fill_common<T, S>(h, a);
+    if (y_dev) {
+      a.y_dev = reinterpret_cast<const T*>(y_dev);
+    } else {
+      for (int j = 0; j < h->d; ++j) a.y_val[j] = (T)y_host[j];
+    }
+    a.t = (uint32_t)h->t;
+    a.k = k;
+    a.u = (uint32_t)h->u;
+    a.flags = kStepWeight | kStepPropagate;
+    a.utau = (uint32_t)h->t + 1u;
+    a.radix = sp.r;
+    a.log2r = sp.log2r;
+    a.lnr = (T)std::log((double)sp.r);
     a.ntiles = h->g_ntiles;
     a.lw_nonzero = h->lw_zero ? 0 : 1;
     LaunchReq rq{};
@@ -208,7 +241,7 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.nt = (int)h->g_nt;
     rq.ppt = (int)h->g_ppt;
     rq.grid = h->g_ntiles;
-    e = launch(h, rq, &a);
+    hipError_t e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global weight launch");
     rq.what = LW_GLOBAL_PREFIX;
     rq.nt = 256;
@@ -225,15 +258,36 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.tile_elems = h->g_tile;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global draw launch");
+    // the global path does not store log-weights: after it every one is 0
+    h->cur ^= 1;
+    h->u += 1;
+    h->lw_zero = true;
+    fs.k = k;
+    fs.radix = (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu);
+    fs.ntiles = h->g_ntiles;
+  } else if (!h->full_cycle) {
+    const uint32_t k = (uint32_t)(h->t % S_);
+    pf_status st = launch_stage<T, S>(h, y_host, y_dev, k, kStepWeight | kStepPropagate, (uint32_t)h->t + 1u);
+    if (st != PF_OK) return st;
+    h->lw_zero = false;
+    fs.k = k;
+    fs.radix = h->stages[k].r;
+    fs.ntiles = h->stages[k].ntiles;
+  } else {
+    if (h->t + 1 >= kStageTau || S_ > 255)
+      return fail(h, PF_E_UNSUPPORTED, "full-cycle steps need t + 1 < 2^24 and S < 256");
+    for (uint32_t k = 0; k < S_; ++k) {
+      const uint32_t flags = (k == 0 ? kStepWeight : 0u) | (k + 1 == S_ ? kStepPropagate : 0u);
+      const uint32_t tau = (uint32_t)h->t + 1u;
+      pf_status st = launch_stage<T, S>(h, y_host, y_dev, k, flags, tau + k * kStageTau);
+      if (st != PF_OK) return st;
+    }
+    h->lw_zero = false;
+    fs.k = S_;
+    fs.radix = (uint32_t)std::min<uint64_t>(h->radix, 0xFFFFFFFFu);
+    fs.ntiles = h->stages[0].ntiles;
   }
-  // the global path does not store log-weights: after it every one is 0
-  h->cur ^= 1;
-  h->lw_zero = h->global;
-  FinStep fs;
-  fs.t = (uint32_t)h->t;
-  fs.k = k;
-  fs.radix = h->global ? (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu) : sp.r;
-  fs.ntiles = h->global ? h->g_ntiles : sp.ntiles;
+  fs.unext = (uint32_t)h->u;
   h->pending.push_back(fs);
   h->t += 1;
   // the ring of partials is full: reduce the pending steps now
@@ -267,6 +321,7 @@ pf_status flush(pf_handle* h) {
     rq.fin.slot = 0u;
     rq.fin.write_rec = 1u;
     rq.fin.use_step_off = 0u;
+    rq.fin.unext = fs.unext;
     rq.fin_part = reinterpret_cast<const char*>(h->partials) + (size_t)(fs.t % h->ring) * h->part_stride * h->tsz;
     rq.fin_ntiles = fs.ntiles;
     hipError_t e = launch(h, rq, dummy);
@@ -471,6 +526,7 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   h->tsz = h->dtype == PF_DTYPE_F64 ? 8 : 4;
   h->ssz = h->dtype == PF_DTYPE_F64 ? 8 : (h->dtype == PF_DTYPE_BF16 ? 2 : 4);
   h->hist_cap = cfg->history ? cfg->history : 1;
+  h->full_cycle = cfg->full_cycle != 0;
   h->model_hash = model_hash(model);
 
   auto bail = [&](pf_status s) {
@@ -511,7 +567,10 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   {
     const uint64_t per = h->part_stride * h->tsz;
     const uint64_t fit = (64ull << 20) / (per ? per : 1);
-    h->ring = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxPending, fit));
+    // full-cycle steps use S offset indices each: the deferred reductions
+    // read the recorded offsets of up to kMaxPending indices
+    const uint64_t per_step = (h->full_cycle && !h->global) ? h->stages.size() : 1;
+    h->ring = (uint32_t)std::max<uint64_t>(1, std::min<uint64_t>(kMaxPending / per_step, fit));
   }
   if ((s = dalloc(h, &h->partials, (size_t)h->ring * h->part_stride * h->tsz)) != PF_OK) return bail(s);
   void* p = nullptr;
@@ -671,7 +730,7 @@ pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_
     // stored log-weights are normalised by the offset the next step would subtract
     double off = -INFINITY;
     for (int sl = 0; sl < kOffSlots; ++sl)
-      off = std::max(off, ord_decode(c.offs[(h->t % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
+      off = std::max(off, ord_decode(c.offs[(h->u % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
     if (h->tsz == 8) {
       double* w = reinterpret_cast<double*>(logw_host);
       for (uint64_t i = 0; i < h->N; ++i) w[i] -= off;
@@ -712,6 +771,7 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   e = hipMemcpy(h->ctl, &c, sizeof(c), hipMemcpyHostToDevice);
   if (e != hipSuccess) return hip_fail(h, e, "control upload");
   h->t = t;
+  h->u = t;
   return PF_OK;
 }
 
@@ -747,7 +807,7 @@ pf_status pf_save(pf_handle* h, void* buf, uint64_t cap, uint64_t* len_out) {
   hd.log_norm = c.log_norm;
   double off = -INFINITY;
   for (int sl = 0; sl < kOffSlots; ++sl)
-    off = std::max(off, ord_decode(c.offs[(h->t % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
+    off = std::max(off, ord_decode(c.offs[(h->u % kOffRing) * kOffSlots * kOffStride + sl * kOffStride]));
   hd.offset = off;
   hd.x_bytes = xb;
   hd.lw_bytes = lb;
@@ -802,6 +862,7 @@ pf_status pf_load(pf_handle* h, const void* buf, uint64_t len) {
   in += lb;
   h->lw_zero = hd.lw_zero != 0;
   h->t = hd.t;
+  h->u = hd.t;
   h->pending.clear();
   Ctl c;
   e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);

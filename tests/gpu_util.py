@@ -118,3 +118,43 @@ def compare_one_step(flt, orc: ButterflyOracle, x_or: np.ndarray, logw_or: np.nd
     return dict(flips=int(mism.sum()), near=int(np.sum(rec_o["margin"] <= MARGIN_TOL)),
                 max_dw=float(np.max(dw)), max_dx=float(np.max(err)) if err.size else 0.0,
                 max_dm=float(np.max(dm / np.maximum(np.abs(rec_o["mean"]), sd))))
+
+
+def compare_full_cycle_step(flt, orc: ButterflyOracle, x_or: np.ndarray, logw_or: np.ndarray, t: int,
+                            y, log_norm: float = 0.0, label: str = ""):
+    """One full-cycle step (all S stages) from the same state on both sides.
+    Estimates, log-normaliser and the (equal) new log-weights are compared
+    everywhere; states where every draw along the particle's ancestry cleared
+    the margin (a flipped draw changes every descendant)."""
+    dtype = flt.dtype
+    tol = tolerances(dtype)
+    xd, wd, xo, wo = round_state(x_or, logw_or, dtype)
+    flt.set_state(xd, wd, t=t, log_norm=log_norm)
+    flt.step(y)
+    rec_g = flt.estimate()
+    xg_raw, wg, tg, lng = flt.get_state()
+    st_o, rec_o = orc.step(State(x=xo, logw=wo, t=t, log_norm=log_norm), y, keep=True)
+    assert tg == t + 1
+    assert rec_g["t"] == t and rec_g["stage"] == orc.S == rec_o["stage"], (rec_g["stage"], orc.S)
+    # after all stages every weight is the global mean: the normalised
+    # log-weights are zero up to rounding
+    dw = np.abs(wg.astype(np.float64) - st_o.logw)
+    assert np.max(dw) <= tol["w_atol"], (label, "logw", float(np.max(dw)))
+    sure = np.ones(flt.n, dtype=bool)
+    for anc, margin in rec_o["stages"]:
+        sure = (margin > MARGIN_TOL) & sure[anc]
+    xg = device_x(flt, xg_raw)
+    err = np.abs(xg[sure] - st_o.x[sure])
+    lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st_o.x[sure])
+    assert np.all(err <= lim), (label, "x", float(np.max(err - lim)))
+    assert np.mean(sure) > 0.5, (label, "too few particles with clear draws", float(np.mean(sure)))
+    sd = np.sqrt(rec_o["var"])
+    dm = np.abs(rec_g["mean"] - rec_o["mean"])
+    assert np.all(dm <= tol["mean_rtol"] * np.maximum(np.abs(rec_o["mean"]), sd)), (label, "mean", dm, sd)
+    dv = np.abs(rec_g["var"] - rec_o["var"])
+    assert np.all(dv <= tol["var_rtol"] * rec_o["var"] + 1e-12), (label, "var", dv, rec_o["var"])
+    assert abs(rec_g["ess"] - rec_o["ess"]) <= tol["ess_rtol"] * rec_o["ess"], (label, "ess")
+    assert abs(lng - rec_o["log_norm"]) <= tol["ln_atol"] * (1 + abs(rec_o["log_norm"] - log_norm)), \
+        (label, "log_norm", lng, rec_o["log_norm"])
+    return dict(sure=float(np.mean(sure)), max_dw=float(np.max(dw)),
+                max_dx=float(np.max(err)) if err.size else 0.0)

@@ -52,7 +52,7 @@ def test_struct_layouts_match_header():
         "pf_model": ("PfModel", ["kind", "d", "A", "Q_chol", "H", "R_chol", "m0", "P0_chol",
                                  "phi", "sigma", "beta"]),
         "pf_config": ("PfConfig", ["n_particles", "radix", "resampler", "state_dtype", "seed",
-                                   "stream_id", "history", "keep_ancestors", "reserved"]),
+                                   "stream_id", "history", "keep_ancestors", "full_cycle"]),
         "pf_estimate_t": ("PfEstimate", ["t", "stage", "radix", "valid", "log_normaliser", "ess",
                                          "max_log_weight", "next_offset", "mean", "var"]),
         "pf_info_t": ("PfInfo", ["n_particles", "d", "n_stages", "radices", "global_path",

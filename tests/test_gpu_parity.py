@@ -256,3 +256,34 @@ def test_history_records_and_errors():
     info = flt.info()
     assert info["stages"] == [4] * 5 and not info["global_path"]
     flt.close()
+
+
+FULL_CASES = [
+    ("ar1", 1024, 4, "multinomial", "f32"),       # S = 5
+    ("ar1", 1024, 2, "multinomial", "f64"),       # S = 10, FP64
+    ("lg4dense", 4096, 8, "systematic", "f32"),   # S = 4, dense model
+    ("sv", 16384, 64, "multinomial", "f32"),      # stages 64, 64, 4
+    ("sv", 16384, 64, "multinomial", "bf16"),
+    ("lg8", 16384, 256, "multinomial", "f32"),    # block-path stages 256, 64
+]
+
+
+@pytest.mark.parametrize("model_name,N,radix,resampler,dtype", FULL_CASES)
+def test_full_cycle_step(model_name, N, radix, resampler, dtype):
+    """Full augmented resampling per step (all S stages of Algorithm 3),
+    teacher-forced against the FP64 oracle at three consecutive steps."""
+    from paper_1812_01502_amd import Filter
+    from tests.gpu_util import compare_full_cycle_step
+    model = MODELS[model_name]()
+    orc = ButterflyOracle(model, N, radix, resampler, seed=7, full_cycle=True)
+    _, ys = W.simulate(model, 6, seed=5)
+    flt = Filter(model, N, radix, resampler=resampler, dtype=dtype, seed=7, history=4, full_cycle=True)
+    st = orc.init()
+    for t in range(5):
+        if t >= 2:
+            label = f"full-cycle {model_name} N={N} r={radix} S={orc.S} {resampler} {dtype} t={t}"
+            log(f"[case] {label}")
+            s = compare_full_cycle_step(flt, orc, st.x, st.logw, t, ys[t], st.log_norm, label)
+            log(f"   ok sure={s['sure']:.4f} dw={s['max_dw']:.2e} dx={s['max_dx']:.2e}")
+        st, _ = orc.step(st, ys[t], keep=False)
+    flt.close()
