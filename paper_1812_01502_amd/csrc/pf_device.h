@@ -368,6 +368,12 @@ constexpr int kDppRowMirror = 0x140;
 constexpr int kDppRowBcast15 = 0x142;
 constexpr int kDppRowBcast31 = 0x143;
 
+// Lane move with every lane's source valid (quad permutes, mirrors): no old
+// value, so the compiler can fuse it into the consuming add or max.
+template <int CTRL> __device__ __forceinline__ float dppm(float v) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
+}
+
 __device__ __forceinline__ float wave_sum(float v) {
   v += dpp_f<kDppQuadXor1>(v);
   v += dpp_f<kDppQuadXor2>(v);

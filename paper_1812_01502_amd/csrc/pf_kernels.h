@@ -402,6 +402,65 @@ __device__ __forceinline__ void step_bookkeeping(const StepArgs<T, S>& a) {
 // Partial sums of one tile from per-thread register values (relative to the
 // tile max `mtile` and the tile reference point `sh`). Thread v < PS of the
 // block writes slot v. `red` needs (NT/64) * PS values of T.
+// Wave sums of NV per-lane FP32 values by recursive halving: at each lane
+// distance (32, 16, then DPP mirror pairs 8, 4 and quad swaps 2, 1) every
+// lane keeps one half of its list (the upper half where the distance bit is
+// set) and adds its partner's copy of that half; once one value is left the
+// remaining distances are plain pair sums. Lane l ends with the wave total
+// of value idx(l) (the sum of the kept upper-half offsets); lanes that differ
+// only in the bits of `group` hold the same total. Fixed order.
+template <int N, int DIST, int NV>
+__device__ __forceinline__ void rh_step_shfl(float (&v)[NV], uint32_t lane, uint32_t& idx, uint32_t& group) {
+  const bool hi = (lane & DIST) != 0u;
+  if constexpr (N == 1) {
+    v[0] += __shfl_xor(v[0], DIST, 64);
+    group |= DIST;
+  } else {
+    constexpr int H = (N + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float a = v[i];
+      const float b = (i + H < N) ? v[i + H] : 0.f;
+      const float recv = __shfl_xor(hi ? a : b, DIST, 64);
+      v[i] = (hi ? b : a) + recv;
+    }
+    if (hi) idx += H;
+  }
+}
+template <int N, int DIST, int CTRL, int NV>
+__device__ __forceinline__ void rh_step_dpp(float (&v)[NV], uint32_t lane, uint32_t& idx, uint32_t& group) {
+  const bool hi = (lane & DIST) != 0u;
+  if constexpr (N == 1) {
+    v[0] += dppm<CTRL>(v[0]);
+    group |= DIST;
+  } else {
+    constexpr int H = (N + 1) / 2;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float a = v[i];
+      const float sa = a + dppm<CTRL>(a);
+      float sb = 0.f;
+      if (i + H < N) sb = v[i + H] + dppm<CTRL>(v[i + H]);
+      v[i] = hi ? sb : sa;
+    }
+    if (hi) idx += H;
+  }
+}
+template <int NV>
+__device__ __forceinline__ float wave_sums_rh(float (&v)[NV], uint32_t lane, uint32_t& idx, uint32_t& group) {
+  constexpr int n1 = (NV + 1) / 2, n2 = (n1 + 1) / 2, n3 = (n2 + 1) / 2, n4 = (n3 + 1) / 2, n5 = (n4 + 1) / 2;
+  static_assert(n5 <= 2, "at most 64 values");
+  idx = 0u;
+  group = 0u;
+  rh_step_shfl<NV, 32>(v, lane, idx, group);
+  rh_step_shfl<n1, 16>(v, lane, idx, group);
+  rh_step_dpp<n2, 8, kDppRowMirror>(v, lane, idx, group);
+  rh_step_dpp<n3, 4, kDppRowHalfMirror>(v, lane, idx, group);
+  rh_step_dpp<n4, 2, kDppQuadXor2>(v, lane, idx, group);
+  rh_step_dpp<n5, 1, kDppQuadXor1>(v, lane, idx, group);
+  return v[0];
+}
+
 template <int D, typename T, int NT, int NLOC>
 __device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[NLOC][D],
                                               const T (&lwn)[NLOC], const T (&sh)[D], int d,
@@ -424,26 +483,43 @@ __device__ __forceinline__ void tile_partials(const T (&l)[NLOC], const T (&x)[N
       a2[j] += wd * dx;
     }
   }
-  s = wave_sum(s);
-  sw2 = wave_sum(sw2);
-  swin = wave_sum(swin);
-#pragma unroll
-  for (int j = 0; j < D; ++j) {
-    if (j < d) {
-      a1[j] = wave_sum(a1[j]);
-      a2[j] = wave_sum(a2[j]);
-    }
-  }
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
-  if (lane == 0) {
-    T* rw = red + wv * PS;
-    rw[1] = s;
-    rw[2] = sw2;
-    rw[3] = swin;
+  if constexpr (sizeof(T) == 4) {
+    // record values 1 .. 3 + 2D in one recursive-halving reduction
+    constexpr int NV = 3 + 2 * D;
+    float v[NV];
+    v[0] = s;
+    v[1] = sw2;
+    v[2] = swin;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
-      rw[4 + j] = a1[j];
-      rw[4 + D + j] = a2[j];
+      v[3 + j] = a1[j];
+      v[3 + D + j] = a2[j];
+    }
+    uint32_t idx, group;
+    const float tot = wave_sums_rh<NV>(v, (uint32_t)lane, idx, group);
+    if (((uint32_t)lane & group) == 0u && idx < (uint32_t)NV) red[wv * PS + 1 + idx] = tot;
+  } else {
+    s = wave_sum(s);
+    sw2 = wave_sum(sw2);
+    swin = wave_sum(swin);
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (j < d) {
+        a1[j] = wave_sum(a1[j]);
+        a2[j] = wave_sum(a2[j]);
+      }
+    }
+    if (lane == 0) {
+      T* rw = red + wv * PS;
+      rw[1] = s;
+      rw[2] = sw2;
+      rw[3] = swin;
+#pragma unroll
+      for (int j = 0; j < D; ++j) {
+        rw[4 + j] = a1[j];
+        rw[4 + D + j] = a2[j];
+      }
     }
   }
   __syncthreads();
@@ -619,11 +695,6 @@ template <int CTRL, int RM, bool BC>
 __device__ __forceinline__ float dppx(float old, float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(__builtin_bit_cast(int, old),
                                                                 __builtin_bit_cast(int, v), CTRL, RM, 0xF, BC));
-}
-// lane move with every lane's source valid (quad permutes, mirrors): no old
-// value, so the compiler can fuse it into the consuming max
-template <int CTRL> __device__ __forceinline__ float dppm(float v) {
-  return __builtin_bit_cast(float, __builtin_amdgcn_mov_dpp(__builtin_bit_cast(int, v), CTRL, 0xF, 0xF, false));
 }
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
