@@ -134,8 +134,9 @@ pf_status plan_batch(pf_batch* b) {
         s.log2C = ilog2(C);
         s.pad = choose_pad(r, C, s.log2R, kBatchNT);
         s.lnr = (float)std::log((double)r);
+        s.xrow = state_row_pitch(C, s.log2R, s.log2C);
         b->stages.push_back(s);
-        c.lds = std::max(c.lds, tile_lds_bytes(F.d, F.D, 4, r, C, s.pad, kBatchNT, false));
+        c.lds = std::max(c.lds, tile_lds_bytes(F.d, F.D, 4, r, C, s.pad, kBatchNT, false, s.xrow));
         R *= r;
       }
     }

@@ -19,13 +19,20 @@ namespace pfh {
 
 using namespace pfk;
 
+// Row pitch of a tile's staged states in LDS: at strides below the tile
+// width consecutive particles fall in consecutive rows, so an odd pitch keeps
+// their writes in different banks; wider strides write along rows.
+inline uint32_t state_row_pitch(uint32_t C, uint32_t log2R, uint32_t log2C) {
+  return log2R < log2C ? C + 1u : C;
+}
+
 struct StagePlan {
   uint32_t r, log2r;
   uint64_t R;
   uint32_t log2R;
   // tile kernel geometry
   int blockpath, nt, ppt;
-  uint32_t C, log2C, pad, ntiles;
+  uint32_t C, log2C, pad, ntiles, xrow;
   size_t lds;
 };
 

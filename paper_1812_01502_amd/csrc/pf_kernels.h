@@ -50,6 +50,7 @@ template <typename T, typename S> struct StepArgs {
   uint32_t d;
   uint64_t N;
   uint32_t log2r, log2R, log2C, pad;  // stage radix, stride, tile columns, LDS row pad
+  uint32_t xrow;             // LDS row pitch of the staged states (C, or C + 1)
   uint32_t t, k;
   uint32_t u;                // offset-slot index: steps, or stages of full-cycle steps
   uint32_t flags;            // kStepWeight | kStepPropagate
@@ -604,13 +605,13 @@ struct LdsCarve {
 
 // LDS bytes of a tile kernel (must match the carve in pf_step_tile).
 __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint32_t r, uint32_t C,
-                                                 uint32_t pad, int NT, bool blockpath) {
+                                                 uint32_t pad, int NT, bool blockpath, uint32_t xrow) {
   const size_t E = (size_t)r * C;
   const size_t P = r + pad;
   const size_t PS = 4 + 3 * (size_t)D;
   size_t b = 0;
   auto add = [&](size_t n) { b = (b + n + 15) & ~(size_t)15; };
-  add((size_t)d * E * tsz);                       // xs
+  add((size_t)d * r * xrow * tsz);                // xs
   add(C * P * tsz);                               // l / cdf
   add(C * P * tsz);                               // uniforms, then ancestor positions
   const size_t red = (size_t)(NT / 64) * PS * tsz;
@@ -862,7 +863,9 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 
   // LDS carve (tile_lds_bytes)
   LdsCarve lc;
-  T* xs = reinterpret_cast<T*>(smem + lc.take((size_t)d * E * sizeof(T)));
+  const uint32_t xrow = a.xrow;
+  const size_t xplane = (size_t)r * xrow;
+  T* xs = reinterpret_cast<T*>(smem + lc.take((size_t)d * xplane * sizeof(T)));
   T* scl = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   T* scu = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   int* sca = reinterpret_cast<int*>(scu);  // positions overwrite the uniforms
@@ -919,7 +922,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     tmax = fmaxT(tmax, lr[e]);
 #pragma unroll
     for (int j = 0; j < D; ++j)
-      if (j < d) xs[(size_t)j * E + (qa[e] << log2C) + ca[e]] = xr[e][j];
+      if (j < d) xs[(size_t)j * xplane + qa[e] * xrow + ca[e]] = xr[e][j];
     scl[ca[e] * P + qa[e]] = lr[e];
     scu[ca[e] * P + qa[e]] = ur[e];
   }
@@ -1038,7 +1041,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const uint32_t pos = (uint32_t)sca[c * P + q];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
-        xh[e][j] = (j < d) ? xs[(size_t)j * E + (pos << log2C) + c] : (T)0;
+        xh[e][j] = (j < d) ? xs[(size_t)j * xplane + pos * xrow + c] : (T)0;
         z[e][j] = 0;
       }
       lwo[e] = colw[c];
@@ -1103,7 +1106,8 @@ __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
 struct BatchStage {   // stage k of one filter
   uint32_t log2r, log2R, log2C, pad;
   float lnr;
-  uint32_t reserved[3];
+  uint32_t xrow;
+  uint32_t reserved[2];
 };
 
 struct BatchFilter {  // one filter of the batch (device table entry)
@@ -1156,6 +1160,7 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   a.log2R = sg.log2R;
   a.log2C = sg.log2C;
   a.pad = sg.pad;
+  a.xrow = sg.xrow;
   a.t = t;
   a.k = k;
   a.u = t;

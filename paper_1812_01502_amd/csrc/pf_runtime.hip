@@ -188,6 +188,7 @@ pf_status launch_stage(pf_handle* h, const double* y_host, const void* y_dev, ui
   a.lnr = (T)std::log((double)sp.r);
   a.log2C = sp.log2C;
   a.pad = sp.pad;
+  a.xrow = sp.xrow;
   a.ntiles = sp.ntiles;
   LaunchReq rq{};
   rq.what = LW_STEP_TILE;
@@ -452,7 +453,8 @@ pf_status plan_stages(pf_handle* h) {
     sp.log2C = ilog2(sp.C);
     sp.ntiles = (uint32_t)(N / E);
     sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
-    sp.lds = tile_lds_bytes(h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0);
+    sp.xrow = state_row_pitch(sp.C, sp.log2R, sp.log2C);
+    sp.lds = tile_lds_bytes(h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0, sp.xrow);
     if (sp.lds > 160 * 1024)
       return fail(h, PF_E_UNSUPPORTED, "tile of radix " + std::to_string(sp.r) + " needs " +
                                            std::to_string(sp.lds) + " bytes of LDS (> 160 KiB)");
