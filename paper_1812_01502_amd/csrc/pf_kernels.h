@@ -548,6 +548,9 @@ struct TileGeo {
   uint32_t log2r, log2R, log2C;
   bool wide;
   uint64_t base;
+  // launch-uniform helpers of pair_coords
+  uint32_t sq, sh2, mlo, rmask;
+  bool r1;  // narrow with R = 1: a pair's second particle is in the next row
 };
 
 __device__ __forceinline__ TileGeo tile_geo(uint32_t tile, uint32_t log2r, uint32_t log2R,
@@ -565,23 +568,24 @@ __device__ __forceinline__ TileGeo tile_geo(uint32_t tile, uint32_t log2r, uint3
   } else {
     g.base = (uint64_t)tile << (log2r + log2C);
   }
+  g.sq = g.wide ? log2C : log2R;
+  g.sh2 = g.sq + log2r;
+  g.mlo = (1u << (g.wide ? log2C : log2R)) - 1u;
+  g.rmask = (1u << log2r) - 1u;
+  g.r1 = !g.wide && log2R == 0u;
   return g;
 }
 
-__device__ __forceinline__ void tile_coords(const TileGeo& g, uint32_t f, uint32_t& q, uint32_t& c,
-                                            uint64_t& gi) {
-  if (g.wide) {
-    q = f >> g.log2C;
-    c = f & ((1u << g.log2C) - 1u);
-    gi = g.base + ((uint64_t)q << g.log2R) + c;
-  } else {
-    const uint32_t sh = g.log2r + g.log2R;
-    const uint32_t hb = f >> sh;
-    const uint32_t rem = f & ((1u << sh) - 1u);
-    q = rem >> g.log2R;
-    c = (hb << g.log2R) | (rem & ((1u << g.log2R) - 1u));
-    gi = g.base + f;
-  }
+// Row q, column c and global index of the particles at even tile position f
+// and f + 1 (one branch-free formula for wide and narrow tiles: for a wide
+// tile f >> sh2 is 0; the pair's global indices are gi and gi + 1).
+__device__ __forceinline__ void pair_coords(const TileGeo& g, uint32_t f, uint32_t& q0, uint32_t& c0,
+                                            uint32_t& q1, uint32_t& c1, uint64_t& gi) {
+  q0 = (f >> g.sq) & g.rmask;
+  c0 = ((f >> g.sh2) << g.log2R) | (f & g.mlo);
+  gi = g.base + (g.wide ? ((uint64_t)q0 << g.log2R) + c0 : (uint64_t)f);
+  q1 = g.r1 ? q0 + 1u : q0;
+  c1 = g.r1 ? c0 : c0 + 1u;
 }
 
 // Tile index of block b. Blocks are dealt
@@ -897,9 +901,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   uint64_t ga[PPT];
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
-    uint64_t g1;
-    tile_coords(geo, 2u * (tid + it * NT), qa[2 * it], ca[2 * it], ga[it]);
-    tile_coords(geo, 2u * (tid + it * NT) + 1, qa[2 * it + 1], ca[2 * it + 1], g1);
+    pair_coords(geo, 2u * (tid + it * NT), qa[2 * it], ca[2 * it], qa[2 * it + 1], ca[2 * it + 1], ga[it]);
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       xr[2 * it][j] = xr[2 * it + 1][j] = 0;
@@ -1031,13 +1033,13 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     const uint32_t f0 = 2u * (tid + it * NT);
     T xh[2][D], z[2][D], lwo[2];
     uint32_t ai[2];
-    uint64_t g0 = 0;
+    uint64_t g0;
+    uint32_t qp[2], cp[2];
+    pair_coords(geo, f0, qp[0], cp[0], qp[1], cp[1], g0);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      uint32_t q, c;
-      uint64_t gi;
-      tile_coords(geo, f0 + e, q, c, gi);  // the pair is gi = g0, g0 + 1
-      if (e == 0) g0 = gi;
+      const uint32_t q = qp[e], c = cp[e];
+      const uint64_t gi = g0 + (uint64_t)e;
       const uint32_t pos = (uint32_t)sca[c * P + q];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
