@@ -112,14 +112,28 @@ struct Words {
   uint32_t w0, w1, w2, w3;
 };
 
+// a ^ b ^ c as one instruction: the three-input bitwise operation of gfx950
+// with truth table 0x96. `c` is wave-uniform (a key word).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c) {
+  uint32_t r;
+  asm("v_bitop3_b32 %0, %1, %2, %3 bitop3:0x96" : "=v"(r) : "v"(a), "v"(b), "s"(c));
+  return r;
+}
+
+// Every caller passes wave-uniform counter words c1, c2, c3 (step, block,
+// stream) and a per-lane c0 (the pair). The first rounds then mix uniform
+// words, which the compiler folds into scalar operations; from the third
+// round on (the second output word: the fourth) both XOR inputs vary per lane,
+// and the two XORs of each output word are one instruction.
 __device__ __forceinline__ Words philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         uint32_t k0, uint32_t k1) {
 #pragma unroll
   for (int i = 0; i < 10; ++i) {
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    const uint32_t n0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
-    const uint32_t n2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    const uint32_t h0 = (uint32_t)(p0 >> 32), h1 = (uint32_t)(p1 >> 32);
+    const uint32_t n0 = i >= 2 ? xor3(h1, c1, k0) : h1 ^ c1 ^ k0;
+    const uint32_t n2 = i >= 3 ? xor3(h0, c3, k1) : h0 ^ c3 ^ k1;
     c1 = (uint32_t)p1;
     c3 = (uint32_t)p0;
     c0 = n0;
