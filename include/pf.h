@@ -102,6 +102,20 @@ typedef struct {
                               Algorithm 3 (full augmented resampling; the
                               output is unweighted, Lemma 3(c)); zero: one
                               stage per step, k = t mod S */
+  uint32_t island;         /* M > 0: the island filter of Section 4
+                              (Algorithm 4, AIRPF) instead of the butterfly
+                              filter: N / M islands of M consecutive
+                              particles, M a power of two, 2 <= M <= N / 2
+                              (M <= 4096; radix is ignored, full_cycle must
+                              be 0). A step weights, resamples within every
+                              island (Algorithm 5, `resampler` applies),
+                              runs the log2(N / M) island stages of
+                              Algorithm 6 (whole islands copied) and
+                              mutates; the output is unweighted. */
+  uint32_t island_swap;    /* island filter only. 0: the no-swap rule of
+                              Algorithm 7 (a pair of islands whose draws
+                              would exchange their samples keeps them);
+                              nonzero: plain Algorithm 6. */
 } pf_config;
 
 /* Estimate of one completed step t (the weighted cloud
@@ -109,8 +123,10 @@ typedef struct {
 typedef struct {
   uint32_t t;              /* step index the record belongs to */
   uint32_t stage;          /* butterfly stage k = t mod S used by the step
-                              (S: a full-cycle step ran every stage) */
-  uint32_t radix;          /* radix r_k of that stage (full cycle: the radix) */
+                              (S: a full-cycle step ran every stage; island
+                              filter: the number of island stages) */
+  uint32_t radix;          /* radix r_k of that stage (full cycle: the radix;
+                              island filter: the island size M) */
   uint32_t valid;          /* 1 if the step has run */
   double log_normaliser;   /* running log p-hat(y_0..y_t), FP64 */
   double ess;              /* (sum w)^2 / (N sum w^2), in [1/N, 1] */

@@ -72,12 +72,16 @@ class Filter:
 
     ``model`` needs the attributes ``kind`` ("lg" or "sv"), ``d`` and, for LG,
     ``A, Q_chol, H, R_chol, m0, P0_chol`` (FP64 arrays); for SV ``phi, sigma,
-    beta``. ``radix >= n`` selects the global bootstrap filter.
+    beta``. ``radix >= n`` selects the global bootstrap filter. ``island = M``
+    selects the island filter (AIRPF) with islands of M particles (radix is
+    then ignored); ``island_swap`` runs the plain island stages of Algorithm 6
+    instead of the no-swap rule of Algorithm 7.
     """
 
     def __init__(self, model, n: int, radix: int, resampler: str = "multinomial",
                  dtype: str = "f32", seed: int = 0, stream_id: int = 0, history: int = 1,
-                 keep_ancestors: bool = False, stream: int | None = None, full_cycle: bool = False):
+                 keep_ancestors: bool = False, stream: int | None = None, full_cycle: bool = False,
+                 island: int = 0, island_swap: bool = False):
         self._lib = L.load()
         self.d = int(model.d)
         self.n = int(n)
@@ -94,6 +98,8 @@ class Filter:
         c.history = int(history)
         c.keep_ancestors = 1 if keep_ancestors else 0
         c.full_cycle = 1 if full_cycle else 0
+        c.island = int(island)
+        c.island_swap = 1 if island_swap else 0
         h = ctypes.c_void_p()
         st = self._lib.pf_create(ctypes.byref(m), ctypes.byref(c),
                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))

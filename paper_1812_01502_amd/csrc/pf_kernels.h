@@ -30,6 +30,17 @@ namespace pfk {
 // propagates.
 constexpr uint32_t kStepWeight = 1u;
 constexpr uint32_t kStepPropagate = 2u;
+// Within-island resampling of the island filter (one stage of radix M and
+// stride 1): the launch writes only the ancestor of every particle (into
+// `anc`) and each island's carried log-weight (into `isl_lw`); no states, no
+// per-particle log-weights.
+constexpr uint32_t kStepIsland = 4u;
+// Every incoming log-weight is 0: nothing is read (the offset still applies).
+constexpr uint32_t kStepLwZero = 8u;
+// Counter word 2 of the island-stage uniforms: island stage s draws word 0
+// of the block (island, tau, kIslandBlock + s, stream); particle blocks use
+// counter words below 2^16.
+constexpr uint32_t kIslandBlock = 1u << 16;
 // Uniforms of stage s >= 1 of a full-cycle step come from block 0 of
 // counter word tau + s kStageTau (tau = t + 1 < kStageTau).
 constexpr uint32_t kStageTau = 1u << 24;
@@ -53,7 +64,7 @@ template <typename T, typename S> struct StepArgs {
   uint32_t xrow;             // LDS row pitch of the staged states (C, or C + 1)
   uint32_t t, k;
   uint32_t u;                // offset-slot index: steps, or stages of full-cycle steps
-  uint32_t flags;            // kStepWeight | kStepPropagate
+  uint32_t flags;            // kStepWeight | kStepPropagate | kStepIsland | kStepLwZero
   uint32_t utau;             // counter word of the resampling uniforms (t + 1, or a stage's)
   uint32_t ntiles;
   uint32_t radix;            // r_k (N on the global path)
@@ -61,6 +72,13 @@ template <typename T, typename S> struct StepArgs {
   int32_t systematic;
   int32_t lw_nonzero;        // global path: read logW (else all log-weights are 0)
   T lnr;                     // ln r
+  // island filter: carried log-weight per island (within-island launch),
+  // source island per destination island and within-island ancestors
+  // (island gather launch), log2 of the island size
+  T* isl_lw;
+  const uint32_t* isl_src;
+  const uint32_t* isl_anc;
+  uint32_t log2M;
   // global path scratch
   T* gcdf;                   // within-tile inclusive CDF (N)
   T* gcoarse;                // every 64th CDF value (N / 64)
@@ -615,7 +633,7 @@ __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint3
   const size_t PS = 4 + 3 * (size_t)D;
   size_t b = 0;
   auto add = [&](size_t n) { b = (b + n + 15) & ~(size_t)15; };
-  add((size_t)d * r * xrow * tsz);                // xs
+  add((size_t)d * r * xrow * tsz);                // xs (d = 0: none, the within-island launch)
   add(C * P * tsz);                               // l / cdf
   add(C * P * tsz);                               // uniforms, then ancestor positions
   const size_t red = (size_t)(NT / 64) * PS * tsz;
@@ -869,7 +887,8 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   LdsCarve lc;
   const uint32_t xrow = a.xrow;
   const size_t xplane = (size_t)r * xrow;
-  T* xs = reinterpret_cast<T*>(smem + lc.take((size_t)d * xplane * sizeof(T)));
+  const bool island = (a.flags & kStepIsland) != 0u;
+  T* xs = reinterpret_cast<T*>(smem + lc.take(island ? 0 : (size_t)d * xplane * sizeof(T)));
   T* scl = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   T* scu = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   int* sca = reinterpret_cast<int*>(scu);  // positions overwrite the uniforms
@@ -888,6 +907,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   const T off = (T)read_offset(a.ctl, a.u);
   const bool weight = (a.flags & kStepWeight) != 0u;
   const bool prop = (a.flags & kStepPropagate) != 0u;
+  const bool lwz = (a.flags & kStepLwZero) != 0u;
   T y[D];
 #pragma unroll
   for (int j = 0; j < D; ++j) y[j] = (j < d) ? (a.y_dev ? a.y_dev[j] : a.y_val[j]) : (T)0;
@@ -907,7 +927,11 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       xr[2 * it][j] = xr[2 * it + 1][j] = 0;
       if (j < d) Pair<S, T>::load(a.x_in + (size_t)j * N + ga[it], xr[2 * it][j], xr[2 * it + 1][j]);
     }
-    Pair<T, T>::load(a.lw_in + ga[it], lwn[2 * it], lwn[2 * it + 1]);
+    if (lwz) {
+      lwn[2 * it] = lwn[2 * it + 1] = 0;
+    } else {
+      Pair<T, T>::load(a.lw_in + ga[it], lwn[2 * it], lwn[2 * it + 1]);
+    }
   }
   // block 0 of counter word utau: the step's own (utau = tau) or, for a
   // later stage of a full-cycle step, the stage's (utau = tau + s 2^24),
@@ -922,9 +946,11 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     lwn[e] -= off;
     lr[e] = weight ? lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y) : lwn[e];
     tmax = fmaxT(tmax, lr[e]);
+    if (!island) {
 #pragma unroll
-    for (int j = 0; j < D; ++j)
-      if (j < d) xs[(size_t)j * xplane + qa[e] * xrow + ca[e]] = xr[e][j];
+      for (int j = 0; j < D; ++j)
+        if (j < d) xs[(size_t)j * xplane + qa[e] * xrow + ca[e]] = xr[e][j];
+    }
     scl[ca[e] * P + qa[e]] = lr[e];
     scu[ca[e] * P + qa[e]] = ur[e];
   }
@@ -1022,6 +1048,23 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     for (int w = 1; w < NT / 64; ++w) mx = fmaxT(mx, shx[w]);
     __hip_atomic_fetch_max(off_slot(a.ctl, a.u + 1, tile % kOffSlots), ord_encode((double)mx),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  if (island) {
+    // the within-island launch of the island filter: each particle's
+    // ancestor and, from each island's first member, the island's carried
+    // log-weight (islands are the groups of this stride-1 stage); no states
+#pragma unroll
+    for (int it = 0; it < PPT; ++it) {
+      uint32_t q0, c0, q1, c1;
+      uint64_t g0;
+      pair_coords(geo, 2u * (tid + it * NT), q0, c0, q1, c1, g0);
+      const uint32_t a0 = (uint32_t)((int64_t)g0 + (int64_t)sca[c0 * P + q0] - (int64_t)q0);
+      const uint32_t a1 = (uint32_t)((int64_t)g0 + 1 + (int64_t)sca[c1 * P + q1] - (int64_t)q1);
+      *reinterpret_cast<uint2*>(a.anc + g0) = make_uint2(a0, a1);
+      if (q0 == 0u) a.isl_lw[g0 >> log2r] = colw[c0];
+    }
+    return;
   }
 
   // ---- phase C: gather, then per Philox block: normals, propagate, store ---
@@ -1405,6 +1448,107 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
       a.anc[2 * p] = anc[0];
       a.anc[2 * p + 1] = anc[1];
     }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Island filter (AIRPF, Algorithms 4-7). A step is three launches: the step
+// tile kernel with kStepIsland (weights, estimate partials, within-island
+// resampling of Algorithm 5, one group of M consecutive particles per
+// island), pf_island_draw (the log2 m stages of Algorithm 6 over islands, with
+// the no-swap rule of Algorithm 7) and pf_island_gather (whole-island copies
+// through the within-island ancestors, then the mutation).
+// ---------------------------------------------------------------------------
+// Island arrays (log-weight double + source index) of up to this many bytes
+// are kept in LDS by pf_island_draw.
+constexpr size_t kIslandLdsBytes = 96u * 1024u;
+
+struct IslandArgs {
+  const void* isl_lw;  // carried log-weight per island, compute type
+  double* lv;          // m doubles of scratch (islands beyond the LDS copy)
+  uint32_t* src;       // m: the source island of each destination island (output)
+  uint32_t m, log2m;
+  uint32_t tau, sid, k0, k1;
+  uint32_t no_swap;    // Algorithm 7 (else Algorithm 6)
+  uint32_t use_lds;    // the island arrays live in LDS (12 m bytes)
+};
+
+// One block of 1024 threads. Stage s pairs island lo (bit s clear) with
+// hi = lo + 2^s; each draws, with its own uniform, the island it holds next
+// with probability proportional to the pair's weights (members in index
+// order, first member whose cumulative weight exceeds the target), both then
+// carry the pair mean. With no_swap, a pair whose draws exchange the two
+// samples keeps both in place. One thread owns a pair for the whole stage,
+// so a stage needs no synchronisation inside it.
+template <typename T>
+__global__ void __launch_bounds__(1024) pf_island_draw(IslandArgs ia) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t m = ia.m, tid = threadIdx.x;
+  double* lv = ia.use_lds ? reinterpret_cast<double*>(smem) : ia.lv;
+  uint32_t* src = ia.use_lds ? reinterpret_cast<uint32_t*>(smem + (size_t)m * 8) : ia.src;
+  const T* w = reinterpret_cast<const T*>(ia.isl_lw);
+  for (uint32_t i = tid; i < m; i += 1024u) {
+    lv[i] = (double)w[i];
+    src[i] = i;
+  }
+  __syncthreads();
+  const double ln2 = 0.6931471805599453;
+  for (uint32_t s = 0; s < ia.log2m; ++s) {
+    const uint32_t bit = 1u << s;
+    for (uint32_t p = tid; p < (m >> 1); p += 1024u) {
+      const uint32_t lo = ((p >> s) << (s + 1)) | (p & (bit - 1u)), hi = lo | bit;
+      const double vlo = lv[lo], vhi = lv[hi];
+      const double mx = fmax(vlo, vhi);
+      const double clo = exp(vlo - mx), tot = clo + exp(vhi - mx);
+      const double ulo = word_uniform<double>(philox(lo, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1).w0);
+      const double uhi = word_uniform<double>(philox(hi, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1).w0);
+      uint32_t plo = clo > ulo * tot ? lo : hi;
+      uint32_t phi = clo > uhi * tot ? lo : hi;
+      if (ia.no_swap && plo == hi && phi == lo) {
+        plo = lo;
+        phi = hi;
+      }
+      const uint32_t slo = src[plo], shi = src[phi];
+      const double nv = mx + log(tot) - ln2;
+      src[lo] = slo;
+      src[hi] = shi;
+      lv[lo] = nv;
+      lv[hi] = nv;
+    }
+    __syncthreads();
+  }
+  if (ia.use_lds)
+    for (uint32_t i = tid; i < m; i += 1024u) ia.src[i] = src[i];
+}
+
+// Destination particle kM + j copies particle isl_anc[src[k] M + j] (the
+// within-island draw of its source island), then mutates with the step's
+// normals. One particle pair per thread (a pair never straddles an island).
+template <int D, int MK, typename T, typename S>
+__global__ void __launch_bounds__(256) pf_island_gather(StepArgs<T, S> a) {
+  const int d = (int)a.d;
+  const uint64_t N = a.N, npair = N >> 1;
+  const uint32_t tau = a.t + 1u;
+  const uint64_t mmask = ((uint64_t)1 << a.log2M) - 1u;
+  for (uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x; p < npair; p += (uint64_t)gridDim.x * 256u) {
+    const uint64_t i0 = 2u * p;
+    const uint64_t base = (uint64_t)a.isl_src[i0 >> a.log2M] << a.log2M;
+    const uint2 aa = *reinterpret_cast<const uint2*>(a.isl_anc + base + (i0 & mmask));
+    if (a.anc) *reinterpret_cast<uint2*>(a.anc + i0) = aa;
+    T xh[2][D], z[2][D], xo[2][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      xh[0][j] = (j < d) ? Single<S, T>::load(a.x_in + (size_t)j * N + aa.x) : (T)0;
+      xh[1][j] = (j < d) ? Single<S, T>::load(a.x_in + (size_t)j * N + aa.y) : (T)0;
+      z[0][j] = z[1][j] = 0;
+    }
+    T u0, u1;
+    pair_randoms<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, u0, u1, z[0], z[1]);
+    Model<D, MK, T>::propagate(a.mp, xh[0], z[0], xo[0]);
+    Model<D, MK, T>::propagate(a.mp, xh[1], z[1], xo[1]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + i0, xo[0][j], xo[1][j]);
   }
 }
 

@@ -17,7 +17,9 @@ enum LaunchWhat : int {
   LW_GLOBAL_DRAW = 4,
   LW_FINALIZE = 5,
   LW_FINALIZE_MULTI = 6,
-  LW_FINALIZE_PREFIX = 7
+  LW_FINALIZE_PREFIX = 7,
+  LW_ISLAND_DRAW = 8,
+  LW_ISLAND_GATHER = 9
 };
 
 // What the runtime asks for.
@@ -38,6 +40,8 @@ struct LaunchReq {
   uint32_t fin_ntiles;
   // deferred reductions (LW_FINALIZE_MULTI / LW_FINALIZE_PREFIX)
   const FinMulti* fm;
+  // island stages (LW_ISLAND_DRAW)
+  const IslandArgs* ia;
 };
 
 // Pairs per thread of the butterfly wave path (256 threads) by dimension:
@@ -164,6 +168,17 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
     case LW_FINALIZE: {
       hipLaunchKernelGGL((pf_finalize_kernel<D, T, 512>), dim3(1), dim3(512), 0, st, rq.fin,
                          reinterpret_cast<const T*>(rq.fin_part), rq.fin_ntiles);
+      return hipGetLastError();
+    }
+    case LW_ISLAND_DRAW: {
+      auto k = pf_island_draw<T>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(1), dim3(1024), rq.lds, st, *rq.ia);
+      return hipGetLastError();
+    }
+    case LW_ISLAND_GATHER: {
+      hipLaunchKernelGGL((pf_island_gather<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
       return hipGetLastError();
     }
     case LW_GLOBAL_DRAW: {

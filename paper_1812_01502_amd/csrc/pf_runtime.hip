@@ -55,7 +55,14 @@ struct pf_handle {
   uint64_t u = 0;            // offset-slot index: one per kernel launch of the tile path
   bool full_cycle = false;   // every step runs all S stages
   uint64_t model_hash = 0;   // FNV-1a of the model parameters (checkpoint check)
-  bool lw_zero = true;       // every log-weight is 0 (global path bookkeeping)
+  bool lw_zero = true;       // every log-weight is 0 (global path and island filter)
+  // island filter (AIRPF): islands of M = 2^log2M particles, m = 2^log2m
+  uint32_t island = 0, log2M = 0, log2m = 0;
+  bool island_no_swap = true;
+  uint32_t* ianc = nullptr;  // within-island ancestors (N)
+  void* isl_lw = nullptr;    // carried log-weight per island (m, compute type)
+  uint32_t* isl_src = nullptr;  // source island of each destination island (m)
+  double* isl_lv = nullptr;  // island log-weights when they do not fit in LDS (m)
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
   std::string err;
@@ -207,6 +214,90 @@ pf_status launch_stage(pf_handle* h, const double* y_host, const void* y_dev, ui
   return PF_OK;
 }
 
+// One step of the island filter (Algorithm 4): the within-island launch of
+// the tile kernel (weights, estimate partials, Algorithm 5), the island
+// stages (Algorithm 6 or 7, one block) and the island gather with the
+// mutation. The output is unweighted.
+template <typename T, typename S>
+pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev) {
+  const StagePlan& sp = h->stages[0];
+  StepArgs<T, S> a;
+  fill_common<T, S>(h, a);
+  if (y_dev) {
+    a.y_dev = reinterpret_cast<const T*>(y_dev);
+  } else {
+    for (int j = 0; j < h->d; ++j) a.y_val[j] = (T)y_host[j];
+  }
+  a.t = (uint32_t)h->t;
+  a.k = 0;
+  a.u = (uint32_t)h->u;
+  a.flags = kStepWeight | kStepIsland | (h->lw_zero ? kStepLwZero : 0u);
+  a.utau = (uint32_t)h->t + 1u;
+  a.radix = sp.r;
+  a.log2r = sp.log2r;
+  a.log2R = sp.log2R;
+  a.lnr = (T)std::log((double)sp.r);
+  a.log2C = sp.log2C;
+  a.pad = sp.pad;
+  a.xrow = sp.xrow;
+  a.ntiles = sp.ntiles;
+  a.anc = h->ianc;
+  a.isl_lw = reinterpret_cast<T*>(h->isl_lw);
+  LaunchReq rq{};
+  rq.what = LW_STEP_TILE;
+  rq.D = h->D;
+  rq.mk = h->mk;
+  rq.nt = sp.nt;
+  rq.ppt = sp.ppt;
+  rq.blockpath = sp.blockpath;
+  rq.full = h->d == h->D ? 1 : 0;
+  rq.grid = sp.ntiles;
+  rq.lds = sp.lds;
+  hipError_t e = launch(h, rq, &a);
+  if (e != hipSuccess) return hip_fail(h, e, "within-island launch");
+  h->u += 1;
+
+  const uint32_t m = 1u << h->log2m;
+  IslandArgs ia{};
+  ia.isl_lw = h->isl_lw;
+  ia.lv = h->isl_lv;
+  ia.src = h->isl_src;
+  ia.m = m;
+  ia.log2m = h->log2m;
+  ia.tau = (uint32_t)h->t + 1u;
+  ia.sid = h->sid;
+  ia.k0 = a.k0;
+  ia.k1 = a.k1;
+  ia.no_swap = h->island_no_swap ? 1u : 0u;
+  ia.use_lds = (size_t)m * 12 <= kIslandLdsBytes ? 1u : 0u;
+  LaunchReq rd{};
+  rd.what = LW_ISLAND_DRAW;
+  rd.D = h->D;
+  rd.mk = h->mk;
+  rd.grid = 1;
+  rd.lds = ia.use_lds ? (size_t)m * 12 : 0;
+  rd.ia = &ia;
+  e = launch(h, rd, &a);
+  if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
+
+  StepArgs<T, S> g = a;
+  g.anc = h->anc;
+  g.isl_src = h->isl_src;
+  g.isl_anc = h->ianc;
+  g.log2M = h->log2M;
+  LaunchReq rg{};
+  rg.what = LW_ISLAND_GATHER;
+  rg.D = h->D;
+  rg.mk = h->mk;
+  const uint64_t blocks = (h->N / 2 + 255) / 256;
+  rg.grid = (uint32_t)std::min<uint64_t>(blocks, 65536);
+  e = launch(h, rg, &g);
+  if (e != hipSuccess) return hip_fail(h, e, "island gather launch");
+  h->cur ^= 1;
+  h->lw_zero = true;
+  return PF_OK;
+}
+
 // One time step; y either by value (y_host) or in device memory (y_dev).
 // Rotating mode: stage k = t mod S. Full-cycle mode: stages 0..S-1 in one
 // step (only the first weights, only the last propagates).
@@ -266,6 +357,12 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     fs.k = k;
     fs.radix = (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu);
     fs.ntiles = h->g_ntiles;
+  } else if (h->island) {
+    pf_status st = run_island_step<T, S>(h, y_host, y_dev);
+    if (st != PF_OK) return st;
+    fs.k = h->log2m;
+    fs.radix = h->island;
+    fs.ntiles = h->stages[0].ntiles;
   } else if (!h->full_cycle) {
     const uint32_t k = (uint32_t)(h->t % S_);
     pf_status st = launch_stage<T, S>(h, y_host, y_dev, k, kStepWeight | kStepPropagate, (uint32_t)h->t + 1u);
@@ -399,6 +496,7 @@ pf_status plan_stages(pf_handle* h) {
   const uint32_t last = n - (S - 1) * b;
   uint64_t R = 1;
   for (uint32_t k = 0; k < S; ++k) {
+    if (h->island && k > 0) break;  // the island filter resamples in one stage of radix M, stride 1
     StagePlan sp{};
     sp.log2r = (k + 1 < S) ? b : last;
     sp.r = 1u << sp.log2r;
@@ -454,7 +552,9 @@ pf_status plan_stages(pf_handle* h) {
     sp.ntiles = (uint32_t)(N / E);
     sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
     sp.xrow = state_row_pitch(sp.C, sp.log2R, sp.log2C);
-    sp.lds = tile_lds_bytes(h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0, sp.xrow);
+    // the within-island launch of the island filter stages no states
+    sp.lds = tile_lds_bytes(h->island ? 0 : h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt,
+                            sp.blockpath != 0, sp.xrow);
     if (sp.lds > 160 * 1024)
       return fail(h, PF_E_UNSUPPORTED, "tile of radix " + std::to_string(sp.r) + " needs " +
                                            std::to_string(sp.lds) + " bytes of LDS (> 160 KiB)");
@@ -530,6 +630,22 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   h->hist_cap = cfg->history ? cfg->history : 1;
   h->full_cycle = cfg->full_cycle != 0;
   h->model_hash = model_hash(model);
+  if (cfg->island) {
+    const uint64_t M = cfg->island;
+    if (!is_pow2(M) || M < 2 || M > N / 2 || M > 4096) {
+      delete h;
+      return fail(nullptr, PF_E_INVALID, "island size must be a power of two in [2, min(N / 2, 4096)]");
+    }
+    if (h->full_cycle) {
+      delete h;
+      return fail(nullptr, PF_E_INVALID, "the island filter runs all island stages; full_cycle must be 0");
+    }
+    h->island = (uint32_t)M;
+    h->log2M = ilog2(M);
+    h->log2m = ilog2(N / M);
+    h->island_no_swap = cfg->island_swap == 0;
+    h->radix = M;  // the within-island stage: radix M, stride 1
+  }
 
   auto bail = [&](pf_status s) {
     g_create_error = h->err;
@@ -587,6 +703,16 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   if (cfg->keep_ancestors) {
     if ((s = dalloc(h, &p, (size_t)N * 4)) != PF_OK) return bail(s);
     h->anc = reinterpret_cast<uint32_t*>(p);
+  }
+  if (h->island) {
+    const size_t m = (size_t)1 << h->log2m;
+    if ((s = dalloc(h, &p, (size_t)N * 4)) != PF_OK) return bail(s);
+    h->ianc = reinterpret_cast<uint32_t*>(p);
+    if ((s = dalloc(h, &h->isl_lw, m * h->tsz)) != PF_OK) return bail(s);
+    if ((s = dalloc(h, &p, m * 4)) != PF_OK) return bail(s);
+    h->isl_src = reinterpret_cast<uint32_t*>(p);
+    if ((s = dalloc(h, &p, m * 8)) != PF_OK) return bail(s);
+    h->isl_lv = reinterpret_cast<double*>(p);
   }
   if (h->global) {
     if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz)) != PF_OK) return bail(s);

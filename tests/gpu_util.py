@@ -158,3 +158,71 @@ def compare_full_cycle_step(flt, orc: ButterflyOracle, x_or: np.ndarray, logw_or
         (label, "log_norm", lng, rec_o["log_norm"])
     return dict(sure=float(np.mean(sure)), max_dw=float(np.max(dw)),
                 max_dx=float(np.max(err)) if err.size else 0.0)
+
+
+def island_sure(rec_o, M: int):
+    """Per destination particle: every draw its value depends on cleared the
+    margin (its within-island draw in the source island, and at every island
+    stage both draws of the pair that decided where its island's sample came
+    from: the no-swap rule looks at both)."""
+    stages = rec_o["island_stages"]
+    m = rec_o["src"].shape[0]
+    sure_isl = np.ones(m, dtype=bool)
+    for s, (pick, margin) in enumerate(stages):
+        partner = np.arange(m) ^ (1 << s)
+        pair_ok = (margin > MARGIN_TOL) & (margin[partner] > MARGIN_TOL)
+        sure_isl = pair_ok & sure_isl[pick]
+    N = rec_o["origin"].shape[0]
+    k = np.arange(N) // M
+    j = np.arange(N) % M
+    src = rec_o["src"]
+    return sure_isl[k] & (rec_o["margin"][src[k] * M + j] > MARGIN_TOL)
+
+
+def compare_island_step(flt, orc, x_or: np.ndarray, logw_or: np.ndarray, t: int, y,
+                        log_norm: float = 0.0, label: str = "", upload: bool = True):
+    """One island-filter step from the same state on both sides. Ancestors
+    (the particle each destination copies) and states are compared wherever
+    every draw they depend on cleared the margin; the ancestors of a
+    destination island all lie in one source island; the output is
+    unweighted; estimates and the log-normaliser everywhere. With
+    ``upload=False`` the device already holds the state (its own previous
+    output, whose log-weights are all zero and are then not read)."""
+    dtype = flt.dtype
+    tol = tolerances(dtype)
+    xd, wd, xo, wo = round_state(x_or, logw_or, dtype)
+    if upload:
+        flt.set_state(xd, wd, t=t, log_norm=log_norm)
+    flt.step(y)
+    rec_g = flt.estimate()
+    xg_raw, wg, tg, lng = flt.get_state()
+    anc_g = flt.ancestors().astype(np.int64)
+    st_o, rec_o = orc.step(State(x=xo, logw=wo, t=t, log_norm=log_norm), y, keep=True)
+    M = orc.M
+    assert tg == t + 1
+    assert rec_g["t"] == t and rec_g["stage"] == orc.S_I and rec_g["radix"] == M, (rec_g["stage"], orc.S_I)
+    assert np.all(wg == 0.0), (label, "island output must be unweighted")
+    sure = island_sure(rec_o, M)
+    bad = sure & (anc_g != rec_o["origin"])
+    assert not np.any(bad), (label, "ancestor mismatch", np.nonzero(bad)[0][:8], anc_g[bad][:8],
+                             rec_o["origin"][bad][:8])
+    # whole islands are copied: the ancestors of a destination island all
+    # come from one source island
+    N = flt.n
+    src_g = (anc_g // M).reshape(N // M, M)
+    assert np.all(src_g == src_g[:, :1]), (label, "an island mixes source islands")
+    xg = device_x(flt, xg_raw)
+    err = np.abs(xg[sure] - st_o.x[sure])
+    lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st_o.x[sure])
+    assert np.all(err <= lim), (label, "x", float(np.max(err - lim)))
+    assert np.mean(sure) > 0.5, (label, "too few particles with clear draws", float(np.mean(sure)))
+    sd = np.sqrt(rec_o["var"])
+    dm = np.abs(rec_g["mean"] - rec_o["mean"])
+    assert np.all(dm <= tol["mean_rtol"] * np.maximum(np.abs(rec_o["mean"]), sd)), (label, "mean", dm, sd)
+    dv = np.abs(rec_g["var"] - rec_o["var"])
+    assert np.all(dv <= tol["var_rtol"] * rec_o["var"] + 1e-12), (label, "var", dv, rec_o["var"])
+    assert abs(rec_g["ess"] - rec_o["ess"]) <= tol["ess_rtol"] * rec_o["ess"], (label, "ess")
+    assert abs(lng - rec_o["log_norm"]) <= tol["ln_atol"] * (1 + abs(rec_o["log_norm"] - log_norm)), \
+        (label, "log_norm", lng, rec_o["log_norm"])
+    return dict(sure=float(np.mean(sure)), flips=int(np.sum(anc_g != rec_o["origin"])),
+                max_dx=float(np.max(err)) if err.size else 0.0)

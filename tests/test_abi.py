@@ -52,7 +52,8 @@ def test_struct_layouts_match_header():
         "pf_model": ("PfModel", ["kind", "d", "A", "Q_chol", "H", "R_chol", "m0", "P0_chol",
                                  "phi", "sigma", "beta"]),
         "pf_config": ("PfConfig", ["n_particles", "radix", "resampler", "state_dtype", "seed",
-                                   "stream_id", "history", "keep_ancestors", "full_cycle"]),
+                                   "stream_id", "history", "keep_ancestors", "full_cycle",
+                                   "island", "island_swap"]),
         "pf_estimate_t": ("PfEstimate", ["t", "stage", "radix", "valid", "log_normaliser", "ess",
                                          "max_log_weight", "next_offset", "mean", "var"]),
         "pf_info_t": ("PfInfo", ["n_particles", "d", "n_stages", "radices", "global_path",
@@ -102,7 +103,8 @@ def _cfg(n=1024, radix=2, resampler=0, dtype=0):
 
 @pytest.mark.parametrize("case", ["n_not_pow2", "n_one", "radix_3", "radix_1", "dtype_bad",
                                   "resampler_bad", "d_zero", "d_17", "null_matrix",
-                                  "not_lower", "neg_diag", "nan_entry", "sv_phi"])
+                                  "not_lower", "neg_diag", "nan_entry", "sv_phi",
+                                  "island_3", "island_n", "island_8192", "island_full_cycle"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_1812_01502_amd import _lib as L
     m, keep = _model_lg(2)
@@ -140,6 +142,14 @@ def test_create_rejects_invalid_arguments(lib, case):
     elif case == "sv_phi":
         m = L.PfModel()
         m.kind, m.d, m.phi, m.sigma, m.beta = L.PF_MODEL_SV, 1, 1.0, 0.25, 0.6
+    elif case == "island_3":
+        c.island = 3
+    elif case == "island_n":
+        c.island = 1024                 # one island: at least two are needed
+    elif case == "island_8192":
+        c.n_particles, c.island = 1 << 16, 8192
+    elif case == "island_full_cycle":
+        c.island, c.full_cycle = 64, 1
     h = ctypes.c_void_p()
     st = lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h))
     assert st == -1, (case, st, lib.pf_last_error(None))
@@ -189,6 +199,13 @@ def test_batch_create_rejects_invalid_arguments(lib):
     assert lib.pf_batch_create(ms, cfgs(radix=3), 2, None, ctypes.byref(h)) == -1
     assert lib.pf_batch_create(ms, cfgs(dtype=1), 2, None, ctypes.byref(h)) == -2
     assert b"FP32" in lib.pf_batch_last_error(None)
+    arr = cfgs()
+    arr[1].island = 64
+    assert lib.pf_batch_create(ms, arr, 2, None, ctypes.byref(h)) == -2
+    assert b"island" in lib.pf_batch_last_error(None)
+    arr = cfgs()
+    arr[0].full_cycle = 1
+    assert lib.pf_batch_create(ms, arr, 2, None, ctypes.byref(h)) == -2
     bad = (L.PfModel * 2)(m, m)
     bad[1].d = 0
     assert lib.pf_batch_create(bad, cfgs(), 2, None, ctypes.byref(h)) == -1
