@@ -198,6 +198,22 @@ def serving_bench(window_s: float = 1.0, rate: float = 2000.0, seed: int = 5):
     return stats
 
 
+def island_size(args, N: int) -> int:
+    """Island size of the island-filter section: 1024 particles (LG-8,
+    2^20 particles: 1024 islands), 4096 (SV, 2^24: 4096 islands)."""
+    if args.island:
+        return args.island
+    return min(1024 if args.workload == "lg8" else 4096, N // 2)
+
+
+def island_bytes(d: int, state_bytes: int) -> int:
+    """Bytes one island-filter particle-step must move with its three
+    launches: the within-island launch reads x and writes the ancestor
+    (the incoming log-weights are all zero and not read); the gather reads
+    the ancestor and x and writes x."""
+    return 3 * d * state_bytes + 8
+
+
 def load_traffic(path, n_launch_bytes):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
@@ -228,6 +244,9 @@ def main():
     ap.add_argument("--batch-only", action="store_true", help="print only the batched-filters section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-only", action="store_true", help="print only the serving section")
+    ap.add_argument("--island", type=int, default=0, help="island size of the island-filter section")
+    ap.add_argument("--profile-island", action="store_true",
+                    help="--mode profile: run the island filter instead of the butterfly filter")
     ap.add_argument("--serve-window", type=float, default=1.0, help="arrival window of the serving run (s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -261,9 +280,12 @@ def main():
         return P.Filter(model, N, radix, seed=cfg["seed_pf"], history=4,
                         stream=stream.cuda_stream, full_cycle=full_cycle)
 
+    def make_island(M):
+        return P.Filter(model, N, 2, seed=cfg["seed_pf"], history=4, stream=stream.cuda_stream, island=M)
+
     if args.mode == "profile":
         # step kernels only (for rocprofv3), then a plain copy of known size
-        flt = make(args.radix)
+        flt = make_island(island_size(args, N)) if args.profile_island else make(args.radix)
         flt.run(yd.data_ptr(), Wm, d)
         wall, ev_s = timed_run(flt, yd[Wm:], K, d)
         flt.close()
@@ -325,6 +347,20 @@ def main():
                   "bytes_per_particle_step": S * B,
                   "hbm_frac_algorithmic": S * B * N / (fev / K) / 1e9 / HBM_PEAK_GBS}
 
+    # -- island filter (AIRPF, Algorithms 4-7) ----------------------------------
+    Mi = island_size(args, N)
+    isl = make_island(Mi)
+    isl.run(yd.data_ptr(), Wm, d)
+    iwall, iev = timed_run(isl, yd[Wm:], K, d)
+    isl.close()
+    Bi = island_bytes(d, 4)
+    island = {"island_size": Mi, "islands": N // Mi, "island_stages": (N // Mi).bit_length() - 1,
+              "particle_steps_per_s": N * K / iwall, "ms_per_step": iwall / K * 1e3,
+              "bytes_per_particle_step": Bi,
+              "hbm_frac_algorithmic": Bi * N / (iev / K) / 1e9 / HBM_PEAK_GBS,
+              "speedup_over_global": (N * K / iwall) / gvalue,
+              "launches": "within-island tile kernel, island stages (one block), island gather"}
+
     out = {
         "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
         "value": value,
@@ -355,6 +391,7 @@ def main():
                        "latency_us": {"p50": gp50, "p99": gp99}},
         "per_radix": per_radix,
         "full_cycle": full_cycle,
+        "island": island,
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
     }
     if not args.no_batch and args.mode == "bench":

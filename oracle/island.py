@@ -28,8 +28,9 @@ M powers of two). One time step t with observation y_t (Algorithm 4):
 Random numbers (readings of the paper, which fixes no generator):
 * within-island draws use each particle's ordinary resampling uniform of
   step t (``philox.resample_uniforms`` at tau = t + 1);
-* island draws use ``island_uniforms``: Philox counter (island, tau,
-  ISLAND_BLOCK + s, stream id), word 0 as a 24-bit uniform;
+* island draws use ``island_uniforms``: island i at stage s takes word
+  i mod 4 of the Philox block with counter (floor(i / 4), tau,
+  ISLAND_BLOCK + s, stream id), as a 24-bit uniform;
 * the propagation uses the step's normals (``philox.normals`` at tau).
 """
 from __future__ import annotations
@@ -47,9 +48,9 @@ def island_uniforms(seed: int, stream_id: int, tau: int, m: int, stage: int) -> 
     """Uniform of island ``i < m`` at island stage ``stage`` of the step with
     counter word ``tau``."""
     k0, k1 = philox.seed_key(seed)
-    i = np.arange(m, dtype=np.uint64)
-    w0, _, _, _ = philox.philox4x32_10(i, tau, ISLAND_BLOCK + stage, stream_id, k0, k1)
-    return philox.word_to_uniform(w0)
+    q = np.arange((m + 3) // 4, dtype=np.uint64)
+    w = np.stack(philox.philox4x32_10(q, tau, ISLAND_BLOCK + stage, stream_id, k0, k1), axis=1)
+    return philox.word_to_uniform(w.reshape(-1)[:m])
 
 
 def island_stage(lv: np.ndarray, U: np.ndarray, s: int, no_swap: bool = True):

@@ -722,6 +722,11 @@ __device__ __forceinline__ float dppx(float old, float v) {
 __device__ __forceinline__ float rdlane(float v, int l) {
   return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), l));
 }
+// Value of lane l (wave-uniform l).
+__device__ __forceinline__ float lane_at(float v, uint32_t l) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_readlane(__builtin_bit_cast(int, v), (int)l));
+}
+__device__ __forceinline__ double lane_at(double v, uint32_t l) { return readlane_d(v, (int)l); }
 __device__ __forceinline__ float bperm(uint32_t byte_addr, float v) {
   return __builtin_bit_cast(float, __builtin_amdgcn_ds_bpermute((int)byte_addr, __builtin_bit_cast(int, v)));
 }
@@ -993,8 +998,8 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     __syncthreads();
     for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
       const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      T m = chm[c << lg_nch];
-      for (uint32_t i = 1; i < nch; ++i) m = fmaxT(m, chm[(c << lg_nch) + i]);
+      // the group max over its (at most 64) chunk maxima, one per lane
+      const T m = wave_max((uint32_t)lane < nch ? chm[(c << lg_nch) + lane] : (T)-INFINITY);
       const uint32_t qq = (ch << 6) + lane;
       const T cdf = seg_scan(fexp(scl[c * P + qq] - m), 6u, (uint32_t)lane);
       scl[c * P + qq] = cdf;
@@ -1007,11 +1012,11 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     __syncthreads();
     for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
       const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      T offs = 0, tot = 0;
-      for (uint32_t i = 0; i < nch; ++i) {
-        if (i == ch) offs = tot;
-        tot += chs[(c << lg_nch) + i];
-      }
+      // inclusive scan of the group's chunk totals, one per lane: the
+      // chunk's offset and the group total
+      const T cs = seg_scan((uint32_t)lane < nch ? chs[(c << lg_nch) + lane] : (T)0, 6u, (uint32_t)lane);
+      const T tot = lane_at(cs, nch - 1u);
+      const T offs = ch == 0u ? (T)0 : lane_at(cs, ch - 1u);
       const uint32_t qq = (ch << 6) + lane;
       scl[c * P + qq] += offs;
       if (ch == 0) {
@@ -1459,19 +1464,37 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
 // the no-swap rule of Algorithm 7) and pf_island_gather (whole-island copies
 // through the within-island ancestors, then the mutation).
 // ---------------------------------------------------------------------------
-// Island arrays (log-weight double + source index) of up to this many bytes
-// are kept in LDS by pf_island_draw.
+// Island arrays (log-weight, source index, the stage's uniforms) of up to
+// this many bytes are kept in LDS by pf_island_draw.
 constexpr size_t kIslandLdsBytes = 96u * 1024u;
 
 struct IslandArgs {
   const void* isl_lw;  // carried log-weight per island, compute type
-  double* lv;          // m doubles of scratch (islands beyond the LDS copy)
+  void* lv;            // m values of the compute type: scratch when not in LDS
   uint32_t* src;       // m: the source island of each destination island (output)
   uint32_t m, log2m;
   uint32_t tau, sid, k0, k1;
   uint32_t no_swap;    // Algorithm 7 (else Algorithm 6)
-  uint32_t use_lds;    // the island arrays live in LDS (12 m bytes)
+  uint32_t use_lds;    // the island arrays live in LDS ((sizeof(T) + 8) m bytes)
+  uint32_t uni_all;    // with use_lds: every stage's uniforms are drawn first (4 m log2m bytes more)
 };
+
+// Uniform of island i at island stage s: word i mod 4 of the Philox block
+// (i / 4, tau, kIslandBlock + s, stream).
+__device__ __forceinline__ float island_uniform(const IslandArgs& ia, uint32_t i, uint32_t s) {
+  const Words w = philox(i >> 2, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1);
+  const uint32_t k = i & 3u;
+  return word_uniform<float>(k == 0u ? w.w0 : k == 1u ? w.w1 : k == 2u ? w.w2 : w.w3);
+}
+// All four uniforms of Philox block q of stage s into us[4q .. 4q + 3] (< m).
+__device__ __forceinline__ void island_uniforms4(const IslandArgs& ia, uint32_t q, uint32_t s, float* us) {
+  const Words w = philox(q, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1);
+  const uint32_t i = q << 2;
+  us[i] = word_uniform<float>(w.w0);
+  if (i + 1u < ia.m) us[i + 1u] = word_uniform<float>(w.w1);
+  if (i + 2u < ia.m) us[i + 2u] = word_uniform<float>(w.w2);
+  if (i + 3u < ia.m) us[i + 3u] = word_uniform<float>(w.w3);
+}
 
 // One block of 1024 threads. Stage s pairs island lo (bit s clear) with
 // hi = lo + 2^s; each draws, with its own uniform, the island it holds next
@@ -1479,37 +1502,54 @@ struct IslandArgs {
 // order, first member whose cumulative weight exceeds the target), both then
 // carry the pair mean. With no_swap, a pair whose draws exchange the two
 // samples keeps both in place. One thread owns a pair for the whole stage,
-// so a stage needs no synchronisation inside it.
+// so a stage needs no synchronisation inside it; with the arrays in LDS the
+// uniforms are drawn first by all threads (four islands per Philox block),
+// for every stage at once when they fit.
 template <typename T>
 __global__ void __launch_bounds__(1024) pf_island_draw(IslandArgs ia) {
   extern __shared__ __align__(16) unsigned char smem[];
   const uint32_t m = ia.m, tid = threadIdx.x;
-  double* lv = ia.use_lds ? reinterpret_cast<double*>(smem) : ia.lv;
-  uint32_t* src = ia.use_lds ? reinterpret_cast<uint32_t*>(smem + (size_t)m * 8) : ia.src;
+  const bool in_lds = ia.use_lds != 0u;
+  T* lv = in_lds ? reinterpret_cast<T*>(smem) : reinterpret_cast<T*>(ia.lv);
+  uint32_t* src = in_lds ? reinterpret_cast<uint32_t*>(smem + (size_t)m * sizeof(T)) : ia.src;
+  float* us = reinterpret_cast<float*>(smem + (size_t)m * (sizeof(T) + 4));
   const T* w = reinterpret_cast<const T*>(ia.isl_lw);
   for (uint32_t i = tid; i < m; i += 1024u) {
-    lv[i] = (double)w[i];
+    lv[i] = w[i];
     src[i] = i;
   }
   __syncthreads();
-  const double ln2 = 0.6931471805599453;
+  const T ln2 = (T)0.6931471805599453;
+  const uint32_t nq = (m + 3u) >> 2;
+  const bool all = in_lds && ia.uni_all != 0u;
+  if (all) {
+    // every stage's uniforms at once: independent Philox blocks for all threads
+    for (uint32_t wq = tid; wq < nq * ia.log2m; wq += 1024u)
+      island_uniforms4(ia, wq % nq, wq / nq, us + (size_t)(wq / nq) * m);
+    __syncthreads();
+  }
   for (uint32_t s = 0; s < ia.log2m; ++s) {
     const uint32_t bit = 1u << s;
+    if (in_lds && !all) {
+      for (uint32_t q = tid; q < nq; q += 1024u) island_uniforms4(ia, q, s, us);
+      __syncthreads();
+    }
+    const float* ust = all ? us + (size_t)s * m : us;
     for (uint32_t p = tid; p < (m >> 1); p += 1024u) {
       const uint32_t lo = ((p >> s) << (s + 1)) | (p & (bit - 1u)), hi = lo | bit;
-      const double vlo = lv[lo], vhi = lv[hi];
-      const double mx = fmax(vlo, vhi);
-      const double clo = exp(vlo - mx), tot = clo + exp(vhi - mx);
-      const double ulo = word_uniform<double>(philox(lo, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1).w0);
-      const double uhi = word_uniform<double>(philox(hi, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1).w0);
-      uint32_t plo = clo > ulo * tot ? lo : hi;
-      uint32_t phi = clo > uhi * tot ? lo : hi;
+      const float ulo = in_lds ? ust[lo] : island_uniform(ia, lo, s);
+      const float uhi = in_lds ? ust[hi] : island_uniform(ia, hi, s);
+      const T vlo = lv[lo], vhi = lv[hi];
+      const T mx = fmaxT(vlo, vhi);
+      const T clo = fexp(vlo - mx), tot = clo + fexp(vhi - mx);
+      uint32_t plo = clo > (T)ulo * tot ? lo : hi;
+      uint32_t phi = clo > (T)uhi * tot ? lo : hi;
       if (ia.no_swap && plo == hi && phi == lo) {
         plo = lo;
         phi = hi;
       }
       const uint32_t slo = src[plo], shi = src[phi];
-      const double nv = mx + log(tot) - ln2;
+      const T nv = mx + flog_ge1(tot) - ln2;
       src[lo] = slo;
       src[hi] = shi;
       lv[lo] = nv;
@@ -1517,7 +1557,7 @@ __global__ void __launch_bounds__(1024) pf_island_draw(IslandArgs ia) {
     }
     __syncthreads();
   }
-  if (ia.use_lds)
+  if (in_lds)
     for (uint32_t i = tid; i < m; i += 1024u) ia.src[i] = src[i];
 }
 

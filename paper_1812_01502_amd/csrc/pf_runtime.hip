@@ -62,7 +62,7 @@ struct pf_handle {
   uint32_t* ianc = nullptr;  // within-island ancestors (N)
   void* isl_lw = nullptr;    // carried log-weight per island (m, compute type)
   uint32_t* isl_src = nullptr;  // source island of each destination island (m)
-  double* isl_lv = nullptr;  // island log-weights when they do not fit in LDS (m)
+  void* isl_lv = nullptr;    // island log-weights when they do not fit in LDS (m, compute type)
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
   std::string err;
@@ -269,13 +269,14 @@ pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev)
   ia.k0 = a.k0;
   ia.k1 = a.k1;
   ia.no_swap = h->island_no_swap ? 1u : 0u;
-  ia.use_lds = (size_t)m * 12 <= kIslandLdsBytes ? 1u : 0u;
+  ia.use_lds = (size_t)m * (h->tsz + 8) <= kIslandLdsBytes ? 1u : 0u;
+  ia.uni_all = (size_t)m * (h->tsz + 4 + 4 * (size_t)h->log2m) <= kIslandLdsBytes ? 1u : 0u;
   LaunchReq rd{};
   rd.what = LW_ISLAND_DRAW;
   rd.D = h->D;
   rd.mk = h->mk;
   rd.grid = 1;
-  rd.lds = ia.use_lds ? (size_t)m * 12 : 0;
+  rd.lds = !ia.use_lds ? 0 : (size_t)m * (h->tsz + 4 + (ia.uni_all ? 4 * (size_t)h->log2m : 4));
   rd.ia = &ia;
   e = launch(h, rd, &a);
   if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
@@ -711,8 +712,8 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
     if ((s = dalloc(h, &h->isl_lw, m * h->tsz)) != PF_OK) return bail(s);
     if ((s = dalloc(h, &p, m * 4)) != PF_OK) return bail(s);
     h->isl_src = reinterpret_cast<uint32_t*>(p);
-    if ((s = dalloc(h, &p, m * 8)) != PF_OK) return bail(s);
-    h->isl_lv = reinterpret_cast<double*>(p);
+    if ((s = dalloc(h, &p, m * h->tsz)) != PF_OK) return bail(s);
+    h->isl_lv = p;
   }
   if (h->global) {
     if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz)) != PF_OK) return bail(s);
