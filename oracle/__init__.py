@@ -13,9 +13,10 @@ Modules:
   bpf        the plain bootstrap filter (Algorithms 1 and 2), written apart
   augmented  full S-stage augmented resampling (Algorithm 3) and its exact law
   island     the island filter (AIRPF, Algorithms 4-7)
+  adaptive   ESS-gated stages with a rotating start (Sections 1.2 and 6.4)
   kalman     Kalman filter (closed form for LG models)
   gridfilter point-mass filter for the SV model
 """
-from . import augmented, bpf, butterfly, gridfilter, island, kalman, models, philox, plan  # noqa: F401
+from . import adaptive, augmented, bpf, butterfly, gridfilter, island, kalman, models, philox, plan  # noqa: F401
 from .butterfly import MULTINOMIAL, SYSTEMATIC, ButterflyOracle, State  # noqa: F401
 from .island import IslandOracle  # noqa: F401
