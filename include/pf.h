@@ -116,6 +116,19 @@ typedef struct {
                               Algorithm 7 (a pair of islands whose draws
                               would exchange their samples keeps them);
                               nonzero: plain Algorithm 6. */
+  double ess_threshold;    /* theta in (0, 1]: ESS-gated stages (Section
+                              1.2, the fully adapted scheme, with the
+                              rotating start of Section 6.4). A step
+                              weights, then runs butterfly stages k, k + 1,
+                              ... (mod S) only while the effective sample
+                              size (sum w)^2 / (N sum w^2) of the current
+                              weights is below theta, at most S; k is the
+                              stage after the last one run by an earlier
+                              step (0 at first). The estimate record's
+                              `stage` is the number of stages run. Needs FP32
+                              states, radix <= 64 and below N, N >= 512, no
+                              full_cycle, island or keep_ancestors.
+                              0: off. */
 } pf_config;
 
 /* Estimate of one completed step t (the weighted cloud
@@ -124,7 +137,8 @@ typedef struct {
   uint32_t t;              /* step index the record belongs to */
   uint32_t stage;          /* butterfly stage k = t mod S used by the step
                               (S: a full-cycle step ran every stage; island
-                              filter: the number of island stages) */
+                              filter: the number of island stages; ESS-gated
+                              stages: the number of stages the step ran) */
   uint32_t radix;          /* radix r_k of that stage (full cycle: the radix;
                               island filter: the island size M) */
   uint32_t valid;          /* 1 if the step has run */

@@ -75,13 +75,15 @@ class Filter:
     beta``. ``radix >= n`` selects the global bootstrap filter. ``island = M``
     selects the island filter (AIRPF) with islands of M particles (radix is
     then ignored); ``island_swap`` runs the plain island stages of Algorithm 6
-    instead of the no-swap rule of Algorithm 7.
+    instead of the no-swap rule of Algorithm 7. ``ess_threshold`` in (0, 1]
+    gates the butterfly stages by the effective sample size (Section 1.2)
+    with a rotating start (Section 6.4).
     """
 
     def __init__(self, model, n: int, radix: int, resampler: str = "multinomial",
                  dtype: str = "f32", seed: int = 0, stream_id: int = 0, history: int = 1,
                  keep_ancestors: bool = False, stream: int | None = None, full_cycle: bool = False,
-                 island: int = 0, island_swap: bool = False):
+                 island: int = 0, island_swap: bool = False, ess_threshold: float = 0.0):
         self._lib = L.load()
         self.d = int(model.d)
         self.n = int(n)
@@ -100,6 +102,7 @@ class Filter:
         c.full_cycle = 1 if full_cycle else 0
         c.island = int(island)
         c.island_swap = 1 if island_swap else 0
+        c.ess_threshold = float(ess_threshold)
         h = ctypes.c_void_p()
         st = self._lib.pf_create(ctypes.byref(m), ctypes.byref(c),
                                  ctypes.c_void_p(stream) if stream else None, ctypes.byref(h))

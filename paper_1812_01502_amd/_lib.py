@@ -40,7 +40,7 @@ class PfConfig(ctypes.Structure):
     _fields_ = [("n_particles", c_uint64), ("radix", c_uint64), ("resampler", c_int32),
                 ("state_dtype", c_int32), ("seed", c_uint64), ("stream_id", c_uint32),
                 ("history", c_uint32), ("keep_ancestors", c_uint32), ("full_cycle", c_uint32),
-                ("island", c_uint32), ("island_swap", c_uint32)]
+                ("island", c_uint32), ("island_swap", c_uint32), ("ess_threshold", c_double)]
 
 
 class PfEstimate(ctypes.Structure):

@@ -399,6 +399,7 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
     if (c->keep_ancestors) return bail(bfail(b, PF_E_UNSUPPORTED, who + "keep_ancestors is not batched"));
     if (c->full_cycle) return bail(bfail(b, PF_E_UNSUPPORTED, who + "full-cycle steps are not batched"));
     if (c->island) return bail(bfail(b, PF_E_UNSUPPORTED, who + "the island filter is not batched"));
+    if (c->ess_threshold != 0.0) return bail(bfail(b, PF_E_UNSUPPORTED, who + "ESS-gated stages are not batched"));
     FilterHost& F = b->fh[f];
     F.kind = m->kind;
     F.d = m->d;

@@ -355,7 +355,10 @@ constexpr int kMaxPending = 64;
 struct Ctl {
   double log_norm;           // running log-normaliser (FP64)
   uint32_t t;                // steps reduced so far (diagnostic)
-  uint32_t pad[13];
+  // ESS-gated stages: the next stage slot runs (ad_active), the stage it
+  // runs, stages run so far in the step, the stage the next step starts at
+  uint32_t ad_active, ad_stage, ad_run, ad_next;
+  uint32_t pad[9];
   long long offs[kOffEntries];  // encoded maxima, [ring][slot * stride]
   double step_off[kMaxPending]; // offset step t subtracted, at t mod kMaxPending
   double dlog[kMaxPending];     // log-normaliser increments of deferred reductions

@@ -37,6 +37,22 @@ constexpr uint32_t kStepPropagate = 2u;
 constexpr uint32_t kStepIsland = 4u;
 // Every incoming log-weight is 0: nothing is read (the offset still applies).
 constexpr uint32_t kStepLwZero = 8u;
+// The incoming log-weights are used as stored: no offset is subtracted (an
+// ESS-gated stage after the step's weighting).
+constexpr uint32_t kStepLwRaw = 16u;
+// The launch does not fold its new log-weights into the next step's offset
+// (a later launch of the step writes the final ones).
+constexpr uint32_t kStepNoFold = 32u;
+// Estimate records whose stage field the step's ESS decisions write.
+constexpr uint32_t kStageFromDevice = 0xFFFFFFFFu;
+
+// Geometry of one butterfly stage, for launches that pick their stage on
+// the device (ESS-gated stages).
+struct AdStage {
+  uint32_t log2r, log2R, log2C, pad, xrow, ntiles;
+  float lnr;
+  uint32_t unused;
+};
 // Counter word 2 of the island-stage uniforms: island stage s draws word 0
 // of the block (island, tau, kIslandBlock + s, stream); particle blocks use
 // counter words below 2^16.
@@ -79,6 +95,10 @@ template <typename T, typename S> struct StepArgs {
   const uint32_t* isl_src;
   const uint32_t* isl_anc;
   uint32_t log2M;
+  // ESS-gated stages: per-tile [max, sum w, sum w^2] of the carried weights
+  // (nullable) and the stage table
+  T* ess_out;
+  const AdStage* stab;
   // global path scratch
   T* gcdf;                   // within-tile inclusive CDF (N)
   T* gcoarse;                // every 64th CDF value (N / 64)
@@ -152,6 +172,10 @@ __global__ void __launch_bounds__(256) pf_init_kernel(StepArgs<T, S> a) {
     if (threadIdx.x == 0) {
       a.ctl->log_norm = 0.0;
       a.ctl->t = 0u;
+      a.ctl->ad_active = 0u;
+      a.ctl->ad_stage = 0u;
+      a.ctl->ad_run = 0u;
+      a.ctl->ad_next = 0u;
     }
   }
 }
@@ -331,7 +355,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
     const double ln = ln0 + dlog;
     if (f.write_rec) {
       rec->t = f.t;
-      rec->stage = f.k;
+      if (f.k != kStageFromDevice) rec->stage = f.k;
       rec->radix = f.radix;
       rec->valid = 1u;
       rec->log_normaliser = f.multi ? 0.0 : ln;
@@ -909,7 +933,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 
   const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
   const uint64_t N = a.N;
-  const T off = (T)read_offset(a.ctl, a.u);
+  const T off = (a.flags & kStepLwRaw) != 0u ? (T)0 : (T)read_offset(a.ctl, a.u);
   const bool weight = (a.flags & kStepWeight) != 0u;
   const bool prop = (a.flags & kStepPropagate) != 0u;
   const bool lwz = (a.flags & kStepLwZero) != 0u;
@@ -1047,12 +1071,46 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   tile_lwmax = wave_max(tile_lwmax);
   if (lane == 0) shx[wv] = tile_lwmax;
   __syncthreads();
-  if (tid == 0) {
+  if (tid == 0 && (a.flags & kStepNoFold) == 0u) {
     T mx = shx[0];
 #pragma unroll
     for (int w = 1; w < NT / 64; ++w) mx = fmaxT(mx, shx[w]);
     __hip_atomic_fetch_max(off_slot(a.ctl, a.u + 1, tile % kOffSlots), ord_encode((double)mx),
                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
+
+  if (a.ess_out != nullptr) {
+    // an ESS-gated stage: [max, sum w, sum w^2] of the tile's carried
+    // weights (each group's weight counts for its r members)
+    T mt = shx[0];
+#pragma unroll
+    for (int w = 1; w < NT / 64; ++w) mt = fmaxT(mt, shx[w]);
+    T s1 = 0, s2 = 0;
+    for (uint32_t c = (uint32_t)tid; c < C; c += NT) {
+      const T e = fexp(colw[c] - mt);
+      s1 += e;
+      s2 += e * e;
+    }
+    s1 = wave_sum(s1);
+    s2 = wave_sum(s2);
+    T* scr = scl;  // free after phase B
+    if (lane == 0) {
+      scr[2 * wv] = s1;
+      scr[2 * wv + 1] = s2;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      T t1 = 0, t2 = 0;
+#pragma unroll
+      for (int w = 0; w < NT / 64; ++w) {
+        t1 += scr[2 * w];
+        t2 += scr[2 * w + 1];
+      }
+      T* o = a.ess_out + (size_t)tile * 3;
+      o[0] = mt;
+      o[1] = t1 * (T)r;
+      o[2] = t2 * (T)r;
+    }
   }
 
   if (island) {
@@ -1192,7 +1250,7 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   const uint32_t t = ba.tcur[f];
   const uint32_t k = t % F.S;
   const BatchStage& sg = ba.stages[F.stage0 + k];
-  StepArgs<float, float> a;
+  StepArgs<float, float> a{};  // every field defined: the tile body tests the optional pointers
   a.x_in = F.x[t & 1u];
   a.x_out = F.x[(t + 1u) & 1u];
   a.lw_in = F.lw[t & 1u];
@@ -1590,6 +1648,187 @@ __global__ void __launch_bounds__(256) pf_island_gather(StepArgs<T, S> a) {
     for (int j = 0; j < D; ++j)
       if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + i0, xo[0][j], xo[1][j]);
   }
+}
+
+// ---------------------------------------------------------------------------
+// ESS-gated stages with a rotating start (Section 1.2, Section 6.4), FP32
+// states. A step is a fixed sequence of launches whose work the device
+// decides: pf_adapt_weight (weights, estimate partials; the weighted
+// log-weights stored in place), pf_adapt_decide, then S stage slots, each a
+// pf_adapt_stage (one butterfly stage in place, or nothing) followed by a
+// pf_adapt_decide, then pf_adapt_propagate. The control words live in Ctl.
+// ---------------------------------------------------------------------------
+template <int D, int MK, bool FULL>
+__global__ void __launch_bounds__(256) pf_adapt_weight(StepArgs<float, float> a) {
+  using T = float;
+  constexpr int NT = 256;
+  constexpr int PS = partial_stride(D);
+  __shared__ T red[(NT / 64) * PS];
+  __shared__ T shx[D];
+  if (blockIdx.x == 0) step_bookkeeping(a);
+  const int d = FULL ? D : (int)a.d;
+  const uint64_t N = a.N;
+  const uint64_t i0 = 2u * ((uint64_t)blockIdx.x * NT + threadIdx.x);  // grid: N / 512 blocks
+  T xr[2][D], lwn[2], lr[2], y[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) {
+    xr[0][j] = xr[1][j] = 0;
+    if (j < d) Pair<float, T>::load(a.x_in + (size_t)j * N + i0, xr[0][j], xr[1][j]);
+    y[j] = (j < d) ? (a.y_dev ? a.y_dev[j] : a.y_val[j]) : (T)0;
+  }
+  Pair<T, T>::load(a.lw_in + i0, lwn[0], lwn[1]);
+  const T off = (T)read_offset(a.ctl, a.u);
+  T tmax = -INFINITY;
+#pragma unroll
+  for (int e = 0; e < 2; ++e) {
+    lwn[e] -= off;
+    lr[e] = lwn[e] + Model<D, MK, T>::log_g(a.mp, xr[e], y);
+    tmax = fmaxT(tmax, lr[e]);
+  }
+  Pair<T, T>::store(a.lw_out + i0, lr[0], lr[1]);
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) shx[j] = xr[0][j];
+  }
+  const T mtile = block_max<T, NT>(tmax, red);
+  T sh[D];
+#pragma unroll
+  for (int j = 0; j < D; ++j) sh[j] = shx[j];
+  tile_partials<D, T, NT, 2>(lr, xr, lwn, sh, d, mtile, red, a.part_out + (size_t)blockIdx.x * PS);
+}
+
+// One stage slot: the stage the control block names, in place (the tiles
+// of a stage are disjoint, and each is read whole before it is written), or
+// nothing when the decisions so far stopped the step's resampling.
+template <int D, int MK, int NT, int PPT, bool FULL>
+__global__ void __launch_bounds__(NT) pf_adapt_stage(StepArgs<float, float> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const Ctl* c = a.ctl;
+  if (c->ad_active == 0u) return;
+  const uint32_t k = c->ad_stage;
+  const AdStage g = a.stab[k];
+  if (blockIdx.x >= g.ntiles) return;
+  StepArgs<float, float> b = a;
+  b.k = k;
+  b.log2r = g.log2r;
+  b.log2R = g.log2R;
+  b.log2C = g.log2C;
+  b.pad = g.pad;
+  b.xrow = g.xrow;
+  b.ntiles = g.ntiles;
+  b.radix = 1u << g.log2r;
+  b.lnr = g.lnr;
+  b.utau = a.utau + c->ad_run * kStageTau;
+  step_tile_body<D, MK, float, float, NT, PPT, false, FULL>(b, xcd_tile(blockIdx.x, g.ntiles), smem);
+}
+
+struct AdDecide {
+  Ctl* ctl;
+  const AdStage* stab;
+  const void* rec;        // per-tile records: [m, S, sw2, ...] with `stride` values
+  uint32_t stride;
+  uint32_t ntiles_first;  // tiles of the weighting launch
+  uint32_t first;         // the decision after the weighting (else after a stage slot)
+  uint32_t S, t;
+  uint64_t N;
+  double theta;
+  pf_estimate_t* hist;
+  uint32_t hist_cap;
+};
+
+// ESS of the records (FP64, fixed order) and the next decision: before the
+// first stage, resample only if the ESS is below theta; after a stage, go on
+// with the next stage (cyclically) only while it is below theta and fewer
+// than S stages ran. The step's record gets the number of stages run.
+template <typename T>
+__global__ void __launch_bounds__(256) pf_adapt_decide(AdDecide ad) {
+  __shared__ double sm[256], ss1[256], ss2[256];
+  Ctl* c = ad.ctl;
+  if (!ad.first && c->ad_active == 0u) return;
+  const uint32_t ntiles = ad.first ? ad.ntiles_first : ad.stab[c->ad_stage].ntiles;
+  const int tid = threadIdx.x;
+  double m = -INFINITY, s1 = 0.0, s2 = 0.0;
+  for (uint32_t b = tid; b < ntiles; b += 256u) {
+    const T* r = reinterpret_cast<const T*>(ad.rec) + (size_t)b * ad.stride;
+    const double mb = (double)r[0];
+    if (mb > m) {
+      const double sc = m == -INFINITY ? 0.0 : exp(m - mb);
+      s1 *= sc;
+      s2 *= sc * sc;
+      m = mb;
+    }
+    const double e = mb == -INFINITY ? 0.0 : exp(mb - m);
+    s1 += e * (double)r[1];
+    s2 += e * e * (double)r[2];
+  }
+  sm[tid] = m;
+  ss1[tid] = s1;
+  ss2[tid] = s2;
+  __syncthreads();
+  if (tid != 0) return;
+  double M = -INFINITY;
+  for (int i = 0; i < 256; ++i) M = fmax(M, sm[i]);
+  double S1 = 0.0, S2 = 0.0;
+  for (int i = 0; i < 256; ++i) {
+    const double e = sm[i] == -INFINITY ? 0.0 : exp(sm[i] - M);
+    S1 += e * ss1[i];
+    S2 += e * e * ss2[i];
+  }
+  const double E = S1 * S1 / ((double)ad.N * S2);
+  uint32_t run, stage, active;
+  if (ad.first) {
+    run = 0u;
+    stage = c->ad_next;
+    active = (E < ad.theta) ? 1u : 0u;
+  } else {
+    run = c->ad_run + 1u;
+    stage = (c->ad_stage + 1u) % ad.S;
+    active = (E < ad.theta && run < ad.S) ? 1u : 0u;
+    if (!active) c->ad_next = stage;
+  }
+  c->ad_run = run;
+  c->ad_stage = stage;
+  c->ad_active = active;
+  ad.hist[ad.t % ad.hist_cap].stage = run;
+}
+
+// The mutation after the step's last stage: the gathered states (in place
+// in x_in) propagate with the step's normals into x_out; the carried
+// log-weights are copied along, and their maximum becomes the next step's
+// offset.
+template <int D, int MK>
+__global__ void __launch_bounds__(256) pf_adapt_propagate(StepArgs<float, float> a) {
+  using T = float;
+  __shared__ T red[4];
+  T wmax = -INFINITY;
+  const int d = (int)a.d;
+  const uint64_t N = a.N, npair = N >> 1;
+  const uint32_t tau = a.t + 1u;
+  for (uint64_t p = (uint64_t)blockIdx.x * 256u + threadIdx.x; p < npair; p += (uint64_t)gridDim.x * 256u) {
+    const uint64_t i0 = 2u * p;
+    T xh[2][D], z[2][D], xo[2][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      xh[0][j] = xh[1][j] = 0;
+      if (j < d) Pair<float, T>::load(a.x_in + (size_t)j * N + i0, xh[0][j], xh[1][j]);
+      z[0][j] = z[1][j] = 0;
+    }
+    T u0, u1;
+    pair_randoms<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, u0, u1, z[0], z[1]);
+    Model<D, MK, T>::propagate(a.mp, xh[0], z[0], xo[0]);
+    Model<D, MK, T>::propagate(a.mp, xh[1], z[1], xo[1]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<float, T>::store(a.x_out + (size_t)j * N + i0, xo[0][j], xo[1][j]);
+    T w0, w1;
+    Pair<T, T>::load(a.lw_in + i0, w0, w1);
+    Pair<T, T>::store(a.lw_out + i0, w0, w1);
+    wmax = fmaxT(wmax, fmaxT(w0, w1));
+  }
+  wmax = block_max<T, 256>(wmax, red);
+  if (threadIdx.x == 0)
+    __hip_atomic_fetch_max(off_slot(a.ctl, a.u + 1, blockIdx.x % kOffSlots), ord_encode((double)wmax),
+                           __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 }  // namespace pfk

@@ -5,6 +5,8 @@
 
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "pf_kernels.h"
 
 namespace pfk {
@@ -19,7 +21,11 @@ enum LaunchWhat : int {
   LW_FINALIZE_MULTI = 6,
   LW_FINALIZE_PREFIX = 7,
   LW_ISLAND_DRAW = 8,
-  LW_ISLAND_GATHER = 9
+  LW_ISLAND_GATHER = 9,
+  LW_AD_WEIGHT = 10,
+  LW_AD_STAGE = 11,
+  LW_AD_DECIDE = 12,
+  LW_AD_PROPAGATE = 13
 };
 
 // What the runtime asks for.
@@ -42,6 +48,8 @@ struct LaunchReq {
   const FinMulti* fm;
   // island stages (LW_ISLAND_DRAW)
   const IslandArgs* ia;
+  // ESS decisions (LW_AD_DECIDE)
+  const AdDecide* ad;
 };
 
 // Pairs per thread of the butterfly wave path (256 threads) by dimension:
@@ -170,6 +178,26 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
                          reinterpret_cast<const T*>(rq.fin_part), rq.fin_ntiles);
       return hipGetLastError();
     }
+    case LW_AD_WEIGHT:
+    case LW_AD_STAGE:
+    case LW_AD_DECIDE:
+    case LW_AD_PROPAGATE:
+      if constexpr (std::is_same<T, float>::value && std::is_same<S, float>::value) {
+        if (rq.what == LW_AD_WEIGHT) {
+          hipLaunchKernelGGL((pf_adapt_weight<D, MK, false>), dim3(rq.grid), dim3(256), 0, st, a);
+        } else if (rq.what == LW_AD_STAGE) {
+          auto k = pf_adapt_stage<D, MK, 256, ppt_wave(D), false>;
+          hipError_t e = ensure_lds(k, rq.lds);
+          if (e != hipSuccess) return e;
+          hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+        } else if (rq.what == LW_AD_DECIDE) {
+          hipLaunchKernelGGL(pf_adapt_decide<float>, dim3(1), dim3(256), 0, st, *rq.ad);
+        } else {
+          hipLaunchKernelGGL((pf_adapt_propagate<D, MK>), dim3(rq.grid), dim3(256), 0, st, a);
+        }
+        return hipGetLastError();
+      }
+      return hipErrorInvalidValue;
     case LW_ISLAND_DRAW: {
       auto k = pf_island_draw<T>;
       hipError_t e = ensure_lds(k, rq.lds);

@@ -7,6 +7,7 @@
 #include <cstring>
 #include <new>
 #include <string>
+#include <type_traits>
 #include <vector>
 
 #include "../../include/pf.h"
@@ -63,6 +64,13 @@ struct pf_handle {
   void* isl_lw = nullptr;    // carried log-weight per island (m, compute type)
   uint32_t* isl_src = nullptr;  // source island of each destination island (m)
   void* isl_lv = nullptr;    // island log-weights when they do not fit in LDS (m, compute type)
+  // ESS-gated stages (threshold > 0): stage table, per-tile ESS records of a
+  // stage, the stage slots' grid and LDS, tiles of the weighting launch
+  double ess_theta = 0.0;
+  AdStage* stab = nullptr;
+  void* ess_part = nullptr;
+  uint32_t ad_grid = 0, w_ntiles = 0;
+  size_t ad_lds = 0;
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
   std::string err;
@@ -107,12 +115,13 @@ struct BlobHeader {
   uint64_t n_particles, radix, model_hash, seed;
   int32_t kind, d, resampler, dtype;
   uint32_t stream_id, lw_zero;
+  uint32_t next_stage, reserved;  // ESS-gated stages: where the next resampling starts
   uint64_t t;
   double log_norm, offset;
   uint64_t x_bytes, lw_bytes, rec_bytes;
 };
 constexpr char kBlobMagic[8] = {'P', 'F', 'B', 'F', 'L', 'Y', 'C', 'K'};
-constexpr uint32_t kBlobVersion = 1;
+constexpr uint32_t kBlobVersion = 2;
 
 hipError_t launch(pf_handle* h, const LaunchReq& rq, const void* args) {
   switch (h->dtype) {
@@ -299,6 +308,98 @@ pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev)
   return PF_OK;
 }
 
+// One step with ESS-gated stages (FP32 states): weighting, a decision, S
+// stage slots each followed by a decision (a slot the decisions have closed
+// does nothing), the mutation. The stages run in place on the current
+// buffers; the mutation writes the other pair.
+template <typename T, typename S>
+pf_status run_adaptive_step(pf_handle* h, const double* y_host, const void* y_dev) {
+  if constexpr (!(std::is_same<T, float>::value && std::is_same<S, float>::value)) {
+    return fail(h, PF_E_UNSUPPORTED, "ESS-gated stages need FP32 states");
+  } else {
+    StepArgs<T, S> a;
+    fill_common<T, S>(h, a);
+    if (y_dev) {
+      a.y_dev = reinterpret_cast<const T*>(y_dev);
+    } else {
+      for (int j = 0; j < h->d; ++j) a.y_val[j] = (T)y_host[j];
+    }
+    a.t = (uint32_t)h->t;
+    a.u = (uint32_t)h->u;
+    a.utau = (uint32_t)h->t + 1u;
+    a.lw_out = reinterpret_cast<T*>(h->lw[h->cur]);  // weights stored in place
+    LaunchReq rq{};
+    rq.D = h->D;
+    rq.mk = h->mk;
+    rq.what = LW_AD_WEIGHT;
+    rq.grid = h->w_ntiles;
+    hipError_t e = launch(h, rq, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "weighting launch");
+
+    AdDecide ad{};
+    ad.ctl = h->ctl;
+    ad.stab = h->stab;
+    ad.rec = a.part_out;
+    ad.stride = (uint32_t)partial_stride(h->D);
+    ad.ntiles_first = h->w_ntiles;
+    ad.first = 1u;
+    ad.S = (uint32_t)h->stages.size();
+    ad.t = (uint32_t)h->t;
+    ad.N = h->N;
+    ad.theta = h->ess_theta;
+    ad.hist = h->hist;
+    ad.hist_cap = h->hist_cap;
+    LaunchReq rd{};
+    rd.D = h->D;
+    rd.mk = h->mk;
+    rd.what = LW_AD_DECIDE;
+    rd.ad = &ad;
+    e = launch(h, rd, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "decision launch");
+
+    StepArgs<T, S> b = a;
+    b.x_out = reinterpret_cast<S*>(h->x[h->cur]);  // in place
+    b.lw_in = reinterpret_cast<const T*>(h->lw[h->cur]);
+    b.lw_out = reinterpret_cast<T*>(h->lw[h->cur]);
+    b.flags = kStepLwRaw | kStepNoFold;
+    b.ess_out = reinterpret_cast<T*>(h->ess_part);
+    b.stab = h->stab;
+    b.anc = nullptr;
+    LaunchReq rs{};
+    rs.D = h->D;
+    rs.mk = h->mk;
+    rs.what = LW_AD_STAGE;
+    rs.grid = h->ad_grid;
+    rs.lds = h->ad_lds;
+    ad.first = 0u;
+    ad.rec = h->ess_part;
+    ad.stride = 3u;
+    for (uint32_t j = 0; j < ad.S; ++j) {
+      e = launch(h, rs, &b);
+      if (e != hipSuccess) return hip_fail(h, e, "stage slot launch");
+      e = launch(h, rd, &a);
+      if (e != hipSuccess) return hip_fail(h, e, "decision launch");
+    }
+
+    StepArgs<T, S> c = a;
+    c.x_in = reinterpret_cast<const S*>(h->x[h->cur]);
+    c.x_out = reinterpret_cast<S*>(h->x[h->cur ^ 1]);
+    c.lw_in = reinterpret_cast<const T*>(h->lw[h->cur]);
+    c.lw_out = reinterpret_cast<T*>(h->lw[h->cur ^ 1]);
+    LaunchReq rp{};
+    rp.D = h->D;
+    rp.mk = h->mk;
+    rp.what = LW_AD_PROPAGATE;
+    rp.grid = (uint32_t)std::min<uint64_t>((h->N / 2 + 255) / 256, 65536);
+    e = launch(h, rp, &c);
+    if (e != hipSuccess) return hip_fail(h, e, "mutation launch");
+    h->cur ^= 1;
+    h->u += 1;
+    h->lw_zero = false;
+    return PF_OK;
+  }
+}
+
 // One time step; y either by value (y_host) or in device memory (y_dev).
 // Rotating mode: stage k = t mod S. Full-cycle mode: stages 0..S-1 in one
 // step (only the first weights, only the last propagates).
@@ -358,6 +459,12 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     fs.k = k;
     fs.radix = (uint32_t)std::min<uint64_t>(h->N, 0xFFFFFFFFu);
     fs.ntiles = h->g_ntiles;
+  } else if (h->ess_theta > 0.0) {
+    pf_status st = run_adaptive_step<T, S>(h, y_host, y_dev);
+    if (st != PF_OK) return st;
+    fs.k = kStageFromDevice;
+    fs.radix = (uint32_t)std::min<uint64_t>(h->radix, 0xFFFFFFFFu);
+    fs.ntiles = h->w_ntiles;
   } else if (h->island) {
     pf_status st = run_island_step<T, S>(h, y_host, y_dev);
     if (st != PF_OK) return st;
@@ -631,6 +738,21 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   h->hist_cap = cfg->history ? cfg->history : 1;
   h->full_cycle = cfg->full_cycle != 0;
   h->model_hash = model_hash(model);
+  if (cfg->ess_threshold != 0.0) {
+    const double th = cfg->ess_threshold;
+    std::string why;
+    if (!(th > 0.0 && th <= 1.0)) why = "ess_threshold must be 0 (off) or in (0, 1]";
+    else if (cfg->state_dtype != PF_DTYPE_F32) why = "ESS-gated stages need FP32 states";
+    else if (cfg->radix > 64 || cfg->radix >= N) why = "ESS-gated stages need a radix of at most 64 (and below N)";
+    else if (N < 512) why = "ESS-gated stages need N >= 512";
+    else if (cfg->full_cycle || cfg->island) why = "ESS-gated stages exclude full_cycle and the island filter";
+    else if (cfg->keep_ancestors) why = "ESS-gated stages do not record ancestors";
+    if (!why.empty()) {
+      delete h;
+      return fail(nullptr, PF_E_INVALID, why);
+    }
+    h->ess_theta = th;
+  }
   if (cfg->island) {
     const uint64_t M = cfg->island;
     if (!is_pow2(M) || M < 2 || M > N / 2 || M > 4096) {
@@ -681,6 +803,10 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   }
   uint32_t max_tiles = h->global ? h->g_ntiles : 0;
   for (auto& sp : h->stages) max_tiles = std::max(max_tiles, sp.ntiles);
+  if (h->ess_theta > 0.0) {
+    h->w_ntiles = (uint32_t)(N / 512);
+    max_tiles = std::max(max_tiles, h->w_ntiles);
+  }
   // ring of deferred partials: up to kMaxPending steps within 64 MiB
   h->part_stride = (uint64_t)max_tiles * partial_stride(h->D);
   {
@@ -704,6 +830,23 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   if (cfg->keep_ancestors) {
     if ((s = dalloc(h, &p, (size_t)N * 4)) != PF_OK) return bail(s);
     h->anc = reinterpret_cast<uint32_t*>(p);
+  }
+  if (h->ess_theta > 0.0) {
+    std::vector<AdStage> tab(h->stages.size());
+    uint32_t stage_tiles = 0;
+    for (size_t k = 0; k < h->stages.size(); ++k) {
+      const StagePlan& sp = h->stages[k];
+      if (sp.blockpath || sp.nt != 256) return bail(fail(h, PF_E_UNSUPPORTED, "ESS-gated stages need wave-path tiles"));
+      tab[k] = AdStage{sp.log2r, sp.log2R, sp.log2C, sp.pad, sp.xrow, sp.ntiles, (float)std::log((double)sp.r), 0u};
+      stage_tiles = std::max(stage_tiles, sp.ntiles);
+      h->ad_lds = std::max(h->ad_lds, sp.lds);
+    }
+    h->ad_grid = stage_tiles;
+    if ((s = dalloc(h, &p, tab.size() * sizeof(AdStage))) != PF_OK) return bail(s);
+    h->stab = reinterpret_cast<AdStage*>(p);
+    hipError_t e = hipMemcpy(h->stab, tab.data(), tab.size() * sizeof(AdStage), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bail(hip_fail(h, e, "stage table upload"));
+    if ((s = dalloc(h, &h->ess_part, (size_t)stage_tiles * 3 * h->tsz)) != PF_OK) return bail(s);
   }
   if (h->island) {
     const size_t m = (size_t)1 << h->log2m;
@@ -893,6 +1036,7 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "control copy");
   c.log_norm = log_norm;
+  c.ad_active = c.ad_stage = c.ad_run = c.ad_next = 0u;  // ESS-gated stages start at stage 0
   for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
   c.offs[(t % kOffRing) * kOffSlots * kOffStride] = ord_encode(0.0);
   c.t = t;
@@ -932,6 +1076,7 @@ pf_status pf_save(pf_handle* h, void* buf, uint64_t cap, uint64_t* len_out) {
   hd.dtype = h->dtype;
   hd.stream_id = h->sid;
   hd.lw_zero = h->lw_zero ? 1u : 0u;
+  hd.next_stage = c.ad_next;
   hd.t = h->t;
   hd.log_norm = c.log_norm;
   double off = -INFINITY;
@@ -998,6 +1143,8 @@ pf_status pf_load(pf_handle* h, const void* buf, uint64_t len) {
   if (e != hipSuccess) return hip_fail(h, e, "control copy");
   c.log_norm = hd.log_norm;
   c.t = (uint32_t)hd.t;
+  c.ad_active = c.ad_stage = c.ad_run = 0u;
+  c.ad_next = hd.next_stage < h->stages.size() ? hd.next_stage : 0u;
   for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
   // the raw log-weights come back with the offset the next step subtracts
   c.offs[(hd.t % kOffRing) * kOffSlots * kOffStride] = ord_encode(hd.offset);

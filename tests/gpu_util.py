@@ -226,3 +226,59 @@ def compare_island_step(flt, orc, x_or: np.ndarray, logw_or: np.ndarray, t: int,
         (label, "log_norm", lng, rec_o["log_norm"])
     return dict(sure=float(np.mean(sure)), flips=int(np.sum(anc_g != rec_o["origin"])),
                 max_dx=float(np.max(err)) if err.size else 0.0)
+
+
+ESS_TOL = 1e-3   # ESS decisions are compared where the oracle's ESS is this far (relative) from theta
+
+
+def compare_adaptive_step(flt, orc, st_or, y, label: str = "", upload: bool = True):
+    """One step with ESS-gated stages from the same state on both sides
+    (``st_or``: an oracle ``AdaptiveState``; with ``upload`` it is set on the
+    device, whose rotation then restarts at stage 0, so ``st_or.next_stage``
+    must be 0). The number of stages run must agree (the oracle's ESS values
+    must clear theta by ESS_TOL); states where every draw along the
+    particle's ancestry cleared the margin; the carried log-weights,
+    estimates and log-normaliser everywhere. Returns (new oracle state,
+    statistics)."""
+    from oracle.adaptive import AdaptiveState
+    dtype = flt.dtype
+    tol = tolerances(dtype)
+    xd, wd, xo, wo = round_state(st_or.x, st_or.logw, dtype)
+    if upload:
+        assert st_or.next_stage == 0
+        flt.set_state(xd, wd, t=st_or.t, log_norm=st_or.log_norm)
+    flt.step(y)
+    rec_g = flt.estimate()
+    xg_raw, wg, tg, lng = flt.get_state()
+    st0 = AdaptiveState(x=xo, logw=wo, t=st_or.t, log_norm=st_or.log_norm, next_stage=st_or.next_stage)
+    st_o, rec_o = orc.step(st0, y, keep=True)
+    th = orc.theta
+    # every ESS value that decided something (after S stages the step stops anyway)
+    decisive = rec_o["ess_trace"][:orc.S] if rec_o["stage"] == orc.S else rec_o["ess_trace"]
+    gaps = [abs(e - th) / th for e in decisive]
+    assert min(gaps) > ESS_TOL, (label, "an ESS value is too close to theta for a parity case", rec_o["ess_trace"])
+    assert tg == st_or.t + 1 and rec_g["t"] == st_or.t
+    assert rec_g["stage"] == rec_o["stage"], (label, "stages run", rec_g["stage"], rec_o["stage"], rec_o["ess_trace"])
+    dw = np.abs(wg.astype(np.float64) - st_o.logw)
+    assert np.max(dw) <= tol["w_atol"], (label, "logw", float(np.max(dw)))
+    sure = np.ones(flt.n, dtype=bool)
+    for anc, margin in rec_o["stages"]:
+        sure = (margin > MARGIN_TOL) & sure[anc]
+    xg = device_x(flt, xg_raw)
+    err = np.abs(xg[sure] - st_o.x[sure])
+    lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st_o.x[sure])
+    assert np.all(err <= lim), (label, "x", float(np.max(err - lim)))
+    assert np.mean(sure) > 0.5, (label, "too few particles with clear draws", float(np.mean(sure)))
+    sd = np.sqrt(rec_o["var"])
+    dm = np.abs(rec_g["mean"] - rec_o["mean"])
+    assert np.all(dm <= tol["mean_rtol"] * np.maximum(np.abs(rec_o["mean"]), sd)), (label, "mean", dm, sd)
+    dv = np.abs(rec_g["var"] - rec_o["var"])
+    assert np.all(dv <= tol["var_rtol"] * rec_o["var"] + 1e-12), (label, "var", dv, rec_o["var"])
+    assert abs(rec_g["ess"] - rec_o["ess"]) <= tol["ess_rtol"] * rec_o["ess"], (label, "ess")
+    assert abs(lng - rec_o["log_norm"]) <= tol["ln_atol"] * (1 + abs(rec_o["log_norm"] - st_or.log_norm)), \
+        (label, "log_norm", lng, rec_o["log_norm"])
+    # the next step continues from the device's own state and rotation
+    nxt = AdaptiveState(x=device_x(flt, xg_raw), logw=wg.astype(np.float64), t=tg, log_norm=lng,
+                        next_stage=st_o.next_stage)
+    return nxt, dict(stages=int(rec_o["stage"]), sure=float(np.mean(sure)),
+                     max_dx=float(np.max(err)) if err.size else 0.0)

@@ -53,7 +53,7 @@ def test_struct_layouts_match_header():
                                  "phi", "sigma", "beta"]),
         "pf_config": ("PfConfig", ["n_particles", "radix", "resampler", "state_dtype", "seed",
                                    "stream_id", "history", "keep_ancestors", "full_cycle",
-                                   "island", "island_swap"]),
+                                   "island", "island_swap", "ess_threshold"]),
         "pf_estimate_t": ("PfEstimate", ["t", "stage", "radix", "valid", "log_normaliser", "ess",
                                          "max_log_weight", "next_offset", "mean", "var"]),
         "pf_info_t": ("PfInfo", ["n_particles", "d", "n_stages", "radices", "global_path",
@@ -104,7 +104,9 @@ def _cfg(n=1024, radix=2, resampler=0, dtype=0):
 @pytest.mark.parametrize("case", ["n_not_pow2", "n_one", "radix_3", "radix_1", "dtype_bad",
                                   "resampler_bad", "d_zero", "d_17", "null_matrix",
                                   "not_lower", "neg_diag", "nan_entry", "sv_phi",
-                                  "island_3", "island_n", "island_8192", "island_full_cycle"])
+                                  "island_3", "island_n", "island_8192", "island_full_cycle",
+                                  "ess_negative", "ess_above_one", "ess_bf16", "ess_radix_128",
+                                  "ess_island"])
 def test_create_rejects_invalid_arguments(lib, case):
     from paper_1812_01502_amd import _lib as L
     m, keep = _model_lg(2)
@@ -150,6 +152,16 @@ def test_create_rejects_invalid_arguments(lib, case):
         c.n_particles, c.island = 1 << 16, 8192
     elif case == "island_full_cycle":
         c.island, c.full_cycle = 64, 1
+    elif case == "ess_negative":
+        c.ess_threshold = -0.5
+    elif case == "ess_above_one":
+        c.ess_threshold = 1.5
+    elif case == "ess_bf16":
+        c.ess_threshold, c.state_dtype = 0.5, 1
+    elif case == "ess_radix_128":
+        c.ess_threshold, c.radix = 0.5, 128
+    elif case == "ess_island":
+        c.ess_threshold, c.island = 0.5, 64
     h = ctypes.c_void_p()
     st = lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h))
     assert st == -1, (case, st, lib.pf_last_error(None))
