@@ -214,6 +214,15 @@ def island_bytes(d: int, state_bytes: int) -> int:
     return 3 * d * state_bytes + 8
 
 
+def adaptive_bytes(d: int, state_bytes: int, stages: float) -> float:
+    """Bytes one particle-step with ESS-gated stages must move: the
+    weighting reads x and the log-weight and writes the log-weight; every
+    stage run reads and writes both in place; the mutation reads both and
+    writes both to the other buffers."""
+    row = d * state_bytes + 4
+    return (row + 4) + 2 * row * stages + 2 * row
+
+
 def load_traffic(path, n_launch_bytes):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
@@ -247,6 +256,8 @@ def main():
     ap.add_argument("--island", type=int, default=0, help="island size of the island-filter section")
     ap.add_argument("--profile-island", action="store_true",
                     help="--mode profile: run the island filter instead of the butterfly filter")
+    ap.add_argument("--profile-adaptive", action="store_true",
+                    help="--mode profile: run the ESS-gated filter (theta 0.5) instead")
     ap.add_argument("--serve-window", type=float, default=1.0, help="arrival window of the serving run (s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
@@ -285,7 +296,13 @@ def main():
 
     if args.mode == "profile":
         # step kernels only (for rocprofv3), then a plain copy of known size
-        flt = make_island(island_size(args, N)) if args.profile_island else make(args.radix)
+        if args.profile_island:
+            flt = make_island(island_size(args, N))
+        elif args.profile_adaptive:
+            flt = P.Filter(model, N, args.radix, seed=cfg["seed_pf"], history=4, stream=stream.cuda_stream,
+                           ess_threshold=0.5)
+        else:
+            flt = make(args.radix)
         flt.run(yd.data_ptr(), Wm, d)
         wall, ev_s = timed_run(flt, yd[Wm:], K, d)
         flt.close()
@@ -361,6 +378,22 @@ def main():
               "speedup_over_global": (N * K / iwall) / gvalue,
               "launches": "within-island tile kernel, island stages (one block), island gather"}
 
+    # -- ESS-gated stages with a rotating start (Sections 1.2 and 6.4) ----------
+    theta = 0.5
+    ad = P.Filter(model, N, args.radix, seed=cfg["seed_pf"], history=K, stream=stream.cuda_stream,
+                  ess_threshold=theta)
+    ad.run(yd.data_ptr(), Wm, d)
+    awall, aev = timed_run(ad, yd[Wm:], K, d)
+    stages_run = [int(r["stage"]) for r in ad.history(K)]
+    ad.close()
+    s_mean = float(np.mean(stages_run)) if stages_run else 0.0
+    Ba = adaptive_bytes(d, 4, s_mean)
+    adaptive = {"ess_threshold": theta, "radix": args.radix, "stages_per_step_mean": s_mean,
+                "particle_steps_per_s": N * K / awall, "ms_per_step": awall / K * 1e3,
+                "bytes_per_particle_step": Ba,
+                "hbm_frac_algorithmic": Ba * N / (aev / K) / 1e9 / HBM_PEAK_GBS,
+                "launches_per_step": 3 + 2 * len(plan)}
+
     out = {
         "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
         "value": value,
@@ -392,6 +425,7 @@ def main():
         "per_radix": per_radix,
         "full_cycle": full_cycle,
         "island": island,
+        "adaptive": adaptive,
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
     }
     if not args.no_batch and args.mode == "bench":

@@ -1741,14 +1741,14 @@ struct AdDecide {
 // with the next stage (cyclically) only while it is below theta and fewer
 // than S stages ran. The step's record gets the number of stages run.
 template <typename T>
-__global__ void __launch_bounds__(256) pf_adapt_decide(AdDecide ad) {
-  __shared__ double sm[256], ss1[256], ss2[256];
+__global__ void __launch_bounds__(1024) pf_adapt_decide(AdDecide ad) {
+  __shared__ double wm[16], w1[16], w2[16];
   Ctl* c = ad.ctl;
   if (!ad.first && c->ad_active == 0u) return;
   const uint32_t ntiles = ad.first ? ad.ntiles_first : ad.stab[c->ad_stage].ntiles;
-  const int tid = threadIdx.x;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   double m = -INFINITY, s1 = 0.0, s2 = 0.0;
-  for (uint32_t b = tid; b < ntiles; b += 256u) {
+  for (uint32_t b = tid; b < ntiles; b += 1024u) {
     const T* r = reinterpret_cast<const T*>(ad.rec) + (size_t)b * ad.stride;
     const double mb = (double)r[0];
     if (mb > m) {
@@ -1761,18 +1761,25 @@ __global__ void __launch_bounds__(256) pf_adapt_decide(AdDecide ad) {
     s1 += e * (double)r[1];
     s2 += e * e * (double)r[2];
   }
-  sm[tid] = m;
-  ss1[tid] = s1;
-  ss2[tid] = s2;
+  // waves: common max, fixed-pattern sums; then wave order
+  const double Mw = wave_max(m);
+  const double sc = m == -INFINITY ? 0.0 : exp(m - Mw);
+  s1 = wave_sum(s1 * sc);
+  s2 = wave_sum(s2 * (sc * sc));
+  if (lane == 0) {
+    wm[wv] = Mw;
+    w1[wv] = s1;
+    w2[wv] = s2;
+  }
   __syncthreads();
   if (tid != 0) return;
-  double M = -INFINITY;
-  for (int i = 0; i < 256; ++i) M = fmax(M, sm[i]);
+  double M = wm[0];
+  for (int w = 1; w < 16; ++w) M = fmax(M, wm[w]);
   double S1 = 0.0, S2 = 0.0;
-  for (int i = 0; i < 256; ++i) {
-    const double e = sm[i] == -INFINITY ? 0.0 : exp(sm[i] - M);
-    S1 += e * ss1[i];
-    S2 += e * e * ss2[i];
+  for (int w = 0; w < 16; ++w) {
+    const double e = wm[w] == -INFINITY ? 0.0 : exp(wm[w] - M);
+    S1 += e * w1[w];
+    S2 += e * e * w2[w];
   }
   const double E = S1 * S1 / ((double)ad.N * S2);
   uint32_t run, stage, active;

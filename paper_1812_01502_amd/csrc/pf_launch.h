@@ -191,7 +191,7 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
           if (e != hipSuccess) return e;
           hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
         } else if (rq.what == LW_AD_DECIDE) {
-          hipLaunchKernelGGL(pf_adapt_decide<float>, dim3(1), dim3(256), 0, st, *rq.ad);
+          hipLaunchKernelGGL(pf_adapt_decide<float>, dim3(1), dim3(1024), 0, st, *rq.ad);
         } else {
           hipLaunchKernelGGL((pf_adapt_propagate<D, MK>), dim3(rq.grid), dim3(256), 0, st, a);
         }
