@@ -185,6 +185,9 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       if constexpr (std::is_same<T, float>::value && std::is_same<S, float>::value) {
         if (rq.what == LW_AD_WEIGHT) {
           hipLaunchKernelGGL((pf_adapt_weight<D, MK, false>), dim3(rq.grid), dim3(256), 0, st, a);
+        } else if (rq.what == LW_AD_STAGE && rq.nt == 64) {
+          // small N: the 64-thread tiles of the wave path
+          hipLaunchKernelGGL((pf_adapt_stage<D, MK, 64, 1, false>), dim3(rq.grid), dim3(64), rq.lds, st, a);
         } else if (rq.what == LW_AD_STAGE) {
           auto k = pf_adapt_stage<D, MK, 256, ppt_wave(D), false>;
           hipError_t e = ensure_lds(k, rq.lds);

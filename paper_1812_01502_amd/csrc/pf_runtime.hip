@@ -369,6 +369,7 @@ pf_status run_adaptive_step(pf_handle* h, const double* y_host, const void* y_de
     rs.D = h->D;
     rs.mk = h->mk;
     rs.what = LW_AD_STAGE;
+    rs.nt = h->stages[0].nt;
     rs.grid = h->ad_grid;
     rs.lds = h->ad_lds;
     ad.first = 0u;
@@ -836,7 +837,8 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
     uint32_t stage_tiles = 0;
     for (size_t k = 0; k < h->stages.size(); ++k) {
       const StagePlan& sp = h->stages[k];
-      if (sp.blockpath || sp.nt != 256) return bail(fail(h, PF_E_UNSUPPORTED, "ESS-gated stages need wave-path tiles"));
+      if (sp.blockpath || sp.nt != h->stages[0].nt)
+        return bail(fail(h, PF_E_UNSUPPORTED, "ESS-gated stages need wave-path tiles of one shape"));
       tab[k] = AdStage{sp.log2r, sp.log2R, sp.log2C, sp.pad, sp.xrow, sp.ntiles, (float)std::log((double)sp.r), 0u};
       stage_tiles = std::max(stage_tiles, sp.ntiles);
       h->ad_lds = std::max(h->ad_lds, sp.lds);

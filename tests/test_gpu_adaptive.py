@@ -25,6 +25,7 @@ CASES = [
     ("sv-r32-th0.9", "sv", 1 << 15, 32, 0.9, 3),
     ("lg3-r8-th1", "lg3", 4096, 8, 1.0, 2),
     ("lg4-r16-tiny", "lg4", 1 << 13, 16, 1e-6, 2),
+    ("ar1-small-r4-th0.7", "ar1", 1024, 4, 0.7, 0),   # 64-thread tiles
 ]
 
 
