@@ -592,7 +592,8 @@ struct TileGeo {
   uint64_t base;
   // launch-uniform helpers of pair_coords
   uint32_t sq, sh2, mlo, rmask;
-  bool r1;  // narrow with R = 1: a pair's second particle is in the next row
+  bool r1;  // rows of one particle (narrow with R = 1, or wide with C = 1):
+            // a pair's second particle is in the next row
 };
 
 __device__ __forceinline__ TileGeo tile_geo(uint32_t tile, uint32_t log2r, uint32_t log2R,
@@ -614,7 +615,7 @@ __device__ __forceinline__ TileGeo tile_geo(uint32_t tile, uint32_t log2r, uint3
   g.sh2 = g.sq + log2r;
   g.mlo = (1u << (g.wide ? log2C : log2R)) - 1u;
   g.rmask = (1u << log2r) - 1u;
-  g.r1 = !g.wide && log2R == 0u;
+  g.r1 = g.wide ? log2C == 0u : log2R == 0u;
   return g;
 }
 

@@ -646,6 +646,11 @@ pf_status plan_stages(pf_handle* h) {
       } else if (sp.r == 4096 && h->D <= 4) {
         sp.nt = 1024;
         sp.ppt = 4;
+      } else if (sp.log2R == 0 && sp.r == 2048 && sp.r <= N) {
+        // stride 1: a group is a contiguous run, so a tile of one group still
+        // loads coalesced rows
+        sp.nt = 1024;
+        sp.ppt = 1;
       } else {
         return fail(h, PF_E_UNSUPPORTED,
                     "stage radix " + std::to_string(sp.r) + " is not supported for d = " +
@@ -653,7 +658,7 @@ pf_status plan_stages(pf_handle* h) {
       }
       E = 2u * sp.nt * sp.ppt;
     }
-    if (E > N || E < 2u * sp.r)
+    if (E > N || E < (sp.log2R == 0 ? sp.r : 2u * sp.r))
       return fail(h, PF_E_UNSUPPORTED, "N = " + std::to_string(N) + " is too small for a tile of radix " +
                                            std::to_string(sp.r));
     sp.C = E / sp.r;

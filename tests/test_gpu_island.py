@@ -38,6 +38,7 @@ CASES = [
     ("lg16-f32-M512", "lg16", 1 << 13, 512, "f32", "multinomial", True),
     ("ar1-f32-M2-many", "ar1", 1 << 16, 2, "f32", "multinomial", True),
     ("lg4-f32-M2048-two", "lg4", 4096, 2048, "f32", "multinomial", True),
+    ("lg8-f32-M2048-one-group-tiles", "lg8", 8192, 2048, "f32", "multinomial", True),
 ]
 
 

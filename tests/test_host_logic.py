@@ -57,3 +57,67 @@ def test_slots_for_budget_fits(budget):
         share = budget * shapes[(m, n)] / sum(shapes.values())
         assert c == 1 or c * slot_footprint(dims[m], n) <= share
     assert used <= budget or min(cnt.values()) == 1
+
+
+def test_tile_coordinates_cover_every_particle_once():
+    """The step kernel's tile geometry (tile_geo, pair_coords), compiled for
+    the host from the kernel header: for every radix, stride and tile size
+    the planner can choose (including one group per tile at stride 1), each
+    particle pair's rows and columns lie inside the tile, map back to the
+    pair's global indices, and the tiles of a stage cover every particle
+    exactly once."""
+    import os
+    import re
+    import shutil
+    import subprocess
+    import tempfile
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ker = open(os.path.join(root, "paper_1812_01502_amd", "csrc", "pf_kernels.h")).read()
+    geo = re.search(r"struct TileGeo \{.*?\n\};\n.*?\n}\n.*?pair_coords\(.*?\n}\n", ker, re.S).group(0)
+    src = ("#define __device__\n#define __host__\n#define __forceinline__ inline\n"
+           "#include <cstdint>\n#include <cstdio>\n#include <vector>\n" + geo + r'''
+int main() {
+  long bad = 0, cases = 0;
+  for (uint32_t log2N : {11u, 12u, 13u, 15u})
+  for (uint32_t log2r = 1; log2r <= 12 && log2r < log2N; ++log2r)
+  for (uint32_t log2R = 0; log2R + log2r <= log2N; log2R += (log2R ? log2R : 1))
+  for (uint32_t log2E : {log2r, log2r + 1, 7u, 9u, 10u, 11u, 12u, 13u}) {
+    if (log2E < log2r || log2E > log2N) continue;
+    if (log2E == log2r && log2R != 0) continue;  // one group per tile only at stride 1
+    const uint32_t log2C = log2E - log2r, C = 1u << log2C, r = 1u << log2r, E = 1u << log2E;
+    std::vector<int> seen(1u << log2N, 0);
+    for (uint32_t t = 0; t < (1u << (log2N - log2E)); ++t) {
+      const TileGeo g = tile_geo(t, log2r, log2R, log2C);
+      for (uint32_t f = 0; f < E; f += 2) {
+        uint32_t q0, c0, q1, c1;
+        uint64_t gi;
+        pair_coords(g, f, q0, c0, q1, c1, gi);
+        ++cases;
+        if (q0 >= r || q1 >= r || c0 >= C || c1 >= C || gi + 1 >= (1ull << log2N)) { ++bad; continue; }
+        auto back = [&](uint32_t q, uint32_t c) {
+          return g.base + ((uint64_t)q << log2R) +
+                 (g.wide ? c : ((uint64_t)(c >> log2R) << (log2r + log2R)) + (c & ((1u << log2R) - 1u)));
+        };
+        if (back(q0, c0) != gi || back(q1, c1) != gi + 1) ++bad;
+        seen[gi]++;
+        seen[gi + 1]++;
+      }
+    }
+    for (int v : seen) if (v != 1) { ++bad; break; }
+  }
+  printf("%ld %ld\n", cases, bad);
+  return 0;
+}
+''')
+    d = tempfile.mkdtemp()
+    try:
+        open(os.path.join(d, "g.cpp"), "w").write(src)
+        subprocess.run([cxx, "-O2", "-std=c++17", os.path.join(d, "g.cpp"), "-o", os.path.join(d, "g")], check=True)
+        out = subprocess.run([os.path.join(d, "g")], capture_output=True, text=True, check=True).stdout.split()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    cases, bad = int(out[0]), int(out[1])
+    assert cases > 1_000_000 and bad == 0, (cases, bad)
