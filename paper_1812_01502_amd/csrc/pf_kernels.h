@@ -970,6 +970,25 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   for (int it = 0; it < PPT; ++it)
     pair_block0<T>((uint32_t)(ga[it] >> 1), a.utau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
                    z0r[2 * it], z0r[2 * it + 1]);
+  // one pair per thread and 4 to 8 dimensions: every normal of the step is
+  // drawn here too, while the loads are in flight (none of them depends on
+  // the loaded values); phase C then only gathers, propagates and stores
+  constexpr bool kEarlyZ = PPT == 1 && D >= 4 && D <= 8;
+  T zr[2][kEarlyZ ? D : 1];
+  if constexpr (kEarlyZ) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) zr[0][j] = zr[1][j] = 0;
+    if (prop) {
+      const uint32_t pr = (uint32_t)(ga[0] >> 1);
+      zr[0][0] = z0r[0];
+      zr[1][0] = z0r[1];
+      if (a.utau != tau) {
+        const Words w0 = philox(pr, tau, 0u, a.sid, a.k0, a.k1);
+        box_muller(w0.w2, w0.w3, zr[0][0], zr[1][0]);
+      }
+      pair_normals_rest<D, T>(pr, tau, a.sid, a.k0, a.k1, d, zr[0], zr[1]);
+    }
+  }
   T tmax = -INFINITY;
 #pragma unroll
   for (int e = 0; e < NLOC; ++e) {
@@ -1166,6 +1185,14 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 #pragma unroll
       for (int j = 0; j < D; ++j)
         if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + g0, xh[0][j], xh[1][j]);
+      continue;
+    }
+    if constexpr (kEarlyZ) {
+#pragma unroll
+      for (int j = 0; j < D; ++j)
+        if (j < d)
+          Pair<S, T>::store(a.x_out + (size_t)j * N + g0, Model<D, MK, T>::row(a.mp, xh[0], zr[0], j),
+                            Model<D, MK, T>::row(a.mp, xh[1], zr[1], j));
       continue;
     }
     z[0][0] = z0r[2 * it];
