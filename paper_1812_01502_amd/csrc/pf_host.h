@@ -130,7 +130,11 @@ inline void fill_params(const pf_model* m, int d, ModelParams<T>* P, int* mk_out
 
 // Bank-conflict cost of the LDS pad for the per-group scalar arrays
 // (layout [column][r + pad]): phase-A/C accesses by consecutive pairs and
-// phase-B accesses by group lanes, evaluated for 32 and 64 banks.
+// phase-B accesses by group lanes, evaluated for 32 and 64 banks. For
+// r > 64 member q of a column sits at word q + q / 64 (one skipped word per
+// 64 members, so the lanes of one step of the draw's binary search, which
+// lie a multiple of 64 members apart, fall in distinct banks); the returned
+// pad then includes those r / 64 words.
 inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt);
 
 // Memoised: the batched planner asks for the same geometries many times.
@@ -158,11 +162,13 @@ inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) 
       c = (hb << log2R) | (rem & ((1u << log2R) - 1));
     }
   };
+  const uint32_t skip = r > 64 ? r >> 6 : 0u;
+  auto lix = [&](uint32_t q) { return r > 64 ? q + (q >> 6) : q; };
   uint32_t best = 0;
   double best_cost = 1e30;
   const uint32_t cands[] = {0, 1, 2, 3, 4, 5, 8};
   for (uint32_t pad : cands) {
-    const uint32_t P = r + pad;
+    const uint32_t P = r + skip + pad;
     double cost = 0;
     for (int banks : {32, 64}) {
       auto degree = [&](const std::vector<uint32_t>& addr, int lanes_per_cycle) {
@@ -187,7 +193,7 @@ inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) 
         for (int l = 0; l < 64 && l < nt; ++l) {
           uint32_t q, c;
           coords(2u * l + e, q, c);
-          addr.push_back(c * P + q);
+          addr.push_back(c * P + lix(q));
         }
         cost += degree(addr, lpc);
       }
@@ -207,7 +213,7 @@ inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) 
       best = pad;
     }
   }
-  return best;
+  return skip + best;
 }
 
 // Argument checks of a model (eq. HMM of Section 1.1 as the header states

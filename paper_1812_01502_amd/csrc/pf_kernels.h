@@ -912,6 +912,10 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   const uint32_t E = r << log2C;
   const uint32_t P = r + a.pad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  // word of group member q in its column of scl/scu/sca: for r > 64 one word
+  // is skipped after every 64 members (the pad holds them), so the lanes of
+  // one binary-search step, a multiple of 64 members apart, hit distinct banks
+  auto lix = [](uint32_t q) { return BLOCKPATH ? q + (q >> 6) : q; };
 
   // LDS carve (tile_lds_bytes)
   LdsCarve lc;
@@ -1000,8 +1004,8 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       for (int j = 0; j < D; ++j)
         if (j < d) xs[(size_t)j * xplane + qa[e] * xrow + ca[e]] = xr[e][j];
     }
-    scl[ca[e] * P + qa[e]] = lr[e];
-    scu[ca[e] * P + qa[e]] = ur[e];
+    scl[ca[e] * P + lix(qa[e])] = lr[e];
+    scu[ca[e] * P + lix(qa[e])] = ur[e];
   }
   if (weight) {
     // tile reference point for the variance sums: the tile's first particle
@@ -1036,7 +1040,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     const uint32_t nch = 1u << lg_nch;
     for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
       const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      const T m = wave_max(scl[c * P + (ch << 6) + lane]);
+      const T m = wave_max(scl[c * P + lix((ch << 6) + lane)]);
       if (lane == 0) chm[task] = m;
     }
     __syncthreads();
@@ -1044,7 +1048,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
       // the group max over its (at most 64) chunk maxima, one per lane
       const T m = wave_max((uint32_t)lane < nch ? chm[(c << lg_nch) + lane] : (T)-INFINITY);
-      const uint32_t qq = (ch << 6) + lane;
+      const uint32_t qq = lix((ch << 6) + lane);
       const T cdf = seg_scan(fexp(scl[c * P + qq] - m), 6u, (uint32_t)lane);
       scl[c * P + qq] = cdf;
       if (lane == 63) chs[task] = cdf;
@@ -1061,7 +1065,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const T cs = seg_scan((uint32_t)lane < nch ? chs[(c << lg_nch) + lane] : (T)0, 6u, (uint32_t)lane);
       const T tot = lane_at(cs, nch - 1u);
       const T offs = ch == 0u ? (T)0 : lane_at(cs, ch - 1u);
-      const uint32_t qq = (ch << 6) + lane;
+      const uint32_t qq = lix((ch << 6) + lane);
       scl[c * P + qq] += offs;
       if (ch == 0) {
         const T lw = colm[c] + flog_ge1(tot) - a.lnr;
@@ -1077,13 +1081,13 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
       const uint32_t qq = (ch << 6) + lane;
       const T tot = coltot[c];
-      const T u = scu[c * P + qq];
+      const T u = scu[c * P + lix(qq)];
       const T target = sys ? ((T)qq + colu0[c]) * tot / (T)r : u * tot;
       uint32_t pos = 0;
       for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
-        if (scl[c * P + pos + s - 1u] <= target) pos += s;
+        if (scl[c * P + lix(pos + s - 1u)] <= target) pos += s;
       }
-      sca[c * P + qq] = (int)pos;
+      sca[c * P + lix(qq)] = (int)pos;
     }
   }
   // the next step's offset: max of the new log-weights (deterministic), one
@@ -1142,8 +1146,8 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       uint32_t q0, c0, q1, c1;
       uint64_t g0;
       pair_coords(geo, 2u * (tid + it * NT), q0, c0, q1, c1, g0);
-      const uint32_t a0 = (uint32_t)((int64_t)g0 + (int64_t)sca[c0 * P + q0] - (int64_t)q0);
-      const uint32_t a1 = (uint32_t)((int64_t)g0 + 1 + (int64_t)sca[c1 * P + q1] - (int64_t)q1);
+      const uint32_t a0 = (uint32_t)((int64_t)g0 + (int64_t)sca[c0 * P + lix(q0)] - (int64_t)q0);
+      const uint32_t a1 = (uint32_t)((int64_t)g0 + 1 + (int64_t)sca[c1 * P + lix(q1)] - (int64_t)q1);
       *reinterpret_cast<uint2*>(a.anc + g0) = make_uint2(a0, a1);
       if (q0 == 0u) a.isl_lw[g0 >> log2r] = colw[c0];
     }
@@ -1166,7 +1170,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
     for (int e = 0; e < 2; ++e) {
       const uint32_t q = qp[e], c = cp[e];
       const uint64_t gi = g0 + (uint64_t)e;
-      const uint32_t pos = (uint32_t)sca[c * P + q];
+      const uint32_t pos = (uint32_t)sca[c * P + lix(q)];
 #pragma unroll
       for (int j = 0; j < D; ++j) {
         xh[e][j] = (j < d) ? xs[(size_t)j * xplane + pos * xrow + c] : (T)0;
