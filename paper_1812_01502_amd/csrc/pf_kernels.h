@@ -901,6 +901,24 @@ __device__ __forceinline__ void wave_groups(const T* scl, const T* scu, int* sca
 // ---------------------------------------------------------------------------
 // FULL: the model dimension equals the compiled one (d = D), so every test
 // of a component index against d folds away.
+// Draw of the r > 64 path: the number of members of a group of r = 2^LR
+// whose cumulative weight is <= target, at most r - 1 (binary search).
+// `col` holds member q at word q + q / 64. The search keeps the padded word
+// pp of its lower bound pos: pos is a multiple of 2s at the step of width s,
+// so the probed member pos + s - 1 sits at pp + s - 1 + (s - 1) / 64 and
+// pos + s at pp + s + s / 64 (constants once the loop is unrolled); at the
+// end pos = pp - pp / 65.
+template <int LR, typename T>
+__device__ __forceinline__ uint32_t padded_search(const T* col, T target) {
+  uint32_t pp = 0;
+#pragma unroll
+  for (int k = LR - 1; k >= 0; --k) {
+    const uint32_t s = 1u << k;
+    if (col[pp + (s - 1u) + ((s - 1u) >> 6)] <= target) pp += s + (s >> 6);
+  }
+  return pp - pp / 65u;
+}
+
 template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
 __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const uint32_t tile,
                                                unsigned char* smem) {
@@ -971,9 +989,20 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   // later stage of a full-cycle step, the stage's (utau = tau + s 2^24),
   // whose dimension-0 normals are not used (phase C draws the step's)
 #pragma unroll
-  for (int it = 0; it < PPT; ++it)
-    pair_block0<T>((uint32_t)(ga[it] >> 1), a.utau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
-                   z0r[2 * it], z0r[2 * it + 1]);
+  for (int it = 0; it < PPT; ++it) {
+    if constexpr (BLOCKPATH) {
+      // the dimension-0 normals only where this launch propagates (not in
+      // the within-island launch or an inner full-cycle stage)
+      const Words b0 = philox((uint32_t)(ga[it] >> 1), a.utau, 0u, a.sid, a.k0, a.k1);
+      ur[2 * it] = word_uniform<T>(b0.w0);
+      ur[2 * it + 1] = word_uniform<T>(b0.w1);
+      z0r[2 * it] = z0r[2 * it + 1] = 0;
+      if (prop) box_muller(b0.w2, b0.w3, z0r[2 * it], z0r[2 * it + 1]);
+    } else {
+      pair_block0<T>((uint32_t)(ga[it] >> 1), a.utau, a.sid, a.k0, a.k1, ur[2 * it], ur[2 * it + 1],
+                     z0r[2 * it], z0r[2 * it + 1]);
+    }
+  }
   // one pair per thread and 4 to 8 dimensions: every normal of the step is
   // drawn here too, while the loads are in flight (none of them depends on
   // the loaded values); phase C then only gathers, propagates and stores
@@ -1083,9 +1112,15 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       const T tot = coltot[c];
       const T u = scu[c * P + lix(qq)];
       const T target = sys ? ((T)qq + colu0[c]) * tot / (T)r : u * tot;
-      uint32_t pos = 0;
-      for (uint32_t s = r >> 1; s >= 1u; s >>= 1) {
-        if (scl[c * P + lix(pos + s - 1u)] <= target) pos += s;
+      const T* col = scl + c * P;
+      uint32_t pos;
+      switch (log2r) {
+        case 7: pos = padded_search<7>(col, target); break;
+        case 8: pos = padded_search<8>(col, target); break;
+        case 9: pos = padded_search<9>(col, target); break;
+        case 10: pos = padded_search<10>(col, target); break;
+        case 11: pos = padded_search<11>(col, target); break;
+        default: pos = padded_search<12>(col, target); break;
       }
       sca[c * P + lix(qq)] = (int)pos;
     }
@@ -1557,6 +1592,9 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
 // Island arrays (log-weight, source index, the stage's uniforms) of up to
 // this many bytes are kept in LDS by pf_island_draw.
 constexpr size_t kIslandLdsBytes = 96u * 1024u;
+// Largest source island (d M states) the LDS-staged island gather holds:
+// two blocks still fit a CU.
+constexpr size_t kIslandGatherLds = 64u * 1024u;
 
 struct IslandArgs {
   const void* isl_lw;  // carried log-weight per island, compute type
@@ -1674,6 +1712,56 @@ __global__ void __launch_bounds__(256) pf_island_gather(StepArgs<T, S> a) {
     }
     T u0, u1;
     pair_randoms<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, u0, u1, z[0], z[1]);
+    Model<D, MK, T>::propagate(a.mp, xh[0], z[0], xo[0]);
+    Model<D, MK, T>::propagate(a.mp, xh[1], z[1], xo[1]);
+#pragma unroll
+    for (int j = 0; j < D; ++j)
+      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + i0, xo[0][j], xo[1][j]);
+  }
+}
+
+// The same mutation with one block per destination island k, for islands
+// whose states fit in LDS (d M values): the source island src[k] is staged
+// with coalesced loads, then every ancestor is read from LDS instead of by a
+// scattered global load. Results are those of pf_island_gather.
+constexpr int kIslandGatherNT = 512;
+template <int D, int MK, typename T, typename S>
+__global__ void __launch_bounds__(kIslandGatherNT) pf_island_gather_lds(StepArgs<T, S> a) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  T* xs = reinterpret_cast<T*>(smem);  // [j][member]
+  const int d = (int)a.d;
+  const uint64_t N = a.N;
+  const uint32_t tau = a.t + 1u;
+  const uint32_t M = 1u << a.log2M, half = M >> 1;
+  const uint64_t sbase = (uint64_t)a.isl_src[blockIdx.x] << a.log2M;
+  const uint64_t dbase = (uint64_t)blockIdx.x << a.log2M;
+  for (uint32_t q = threadIdx.x; q < half; q += kIslandGatherNT) {
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      if (j < d) {
+        T v0, v1;
+        Pair<S, T>::load(a.x_in + (size_t)j * N + sbase + 2u * q, v0, v1);
+        xs[(size_t)j * M + 2u * q] = v0;
+        xs[(size_t)j * M + 2u * q + 1u] = v1;
+      }
+    }
+  }
+  __syncthreads();
+  for (uint32_t q = threadIdx.x; q < half; q += kIslandGatherNT) {
+    const uint64_t i0 = dbase + 2u * q;
+    const uint2 aa = *reinterpret_cast<const uint2*>(a.isl_anc + sbase + 2u * q);
+    if (a.anc) *reinterpret_cast<uint2*>(a.anc + i0) = aa;
+    // ancestors of a within-island draw lie in the source island
+    const uint32_t l0 = (uint32_t)(aa.x - sbase), l1 = (uint32_t)(aa.y - sbase);
+    T xh[2][D], z[2][D], xo[2][D];
+#pragma unroll
+    for (int j = 0; j < D; ++j) {
+      xh[0][j] = (j < d) ? xs[(size_t)j * M + l0] : (T)0;
+      xh[1][j] = (j < d) ? xs[(size_t)j * M + l1] : (T)0;
+      z[0][j] = z[1][j] = 0;
+    }
+    T u0, u1;
+    pair_randoms<D, T>((uint32_t)(i0 >> 1), tau, a.sid, a.k0, a.k1, d, u0, u1, z[0], z[1]);
     Model<D, MK, T>::propagate(a.mp, xh[0], z[0], xo[0]);
     Model<D, MK, T>::propagate(a.mp, xh[1], z[1], xo[1]);
 #pragma unroll
@@ -1804,15 +1892,15 @@ __global__ void __launch_bounds__(1024) pf_adapt_decide(AdDecide ad) {
     w2[wv] = s2;
   }
   __syncthreads();
-  if (tid != 0) return;
-  double M = wm[0];
-  for (int w = 1; w < 16; ++w) M = fmax(M, wm[w]);
-  double S1 = 0.0, S2 = 0.0;
-  for (int w = 0; w < 16; ++w) {
-    const double e = wm[w] == -INFINITY ? 0.0 : exp(wm[w] - M);
-    S1 += e * w1[w];
-    S2 += e * e * w2[w];
-  }
+  if (wv != 0) return;
+  // the 16 wave results, one per lane of wave 0 (the rescaling exponentials
+  // run in parallel, not one after another)
+  const double mw = lane < 16 ? wm[lane] : -INFINITY;
+  const double M = wave_max(mw);
+  const double e = mw == -INFINITY ? 0.0 : exp(mw - M);
+  const double S1 = wave_sum(lane < 16 ? e * w1[lane] : 0.0);
+  const double S2 = wave_sum(lane < 16 ? e * e * w2[lane] : 0.0);
+  if (lane != 0) return;
   const double E = S1 * S1 / ((double)ad.N * S2);
   uint32_t run, stage, active;
   if (ad.first) {

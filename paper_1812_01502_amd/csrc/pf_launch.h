@@ -209,7 +209,15 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       return hipGetLastError();
     }
     case LW_ISLAND_GATHER: {
-      hipLaunchKernelGGL((pf_island_gather<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
+      if (rq.lds > 0) {
+        // one block per destination island, its source island staged in LDS
+        auto k = pf_island_gather_lds<D, MK, T, S>;
+        hipError_t e = ensure_lds(k, rq.lds);
+        if (e != hipSuccess) return e;
+        hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kIslandGatherNT), rq.lds, st, a);
+      } else {
+        hipLaunchKernelGGL((pf_island_gather<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
+      }
       return hipGetLastError();
     }
     case LW_GLOBAL_DRAW: {

@@ -7,7 +7,8 @@ oracle, through the C-ABI.
   output is unweighted; a second step continues from the device's own
   unweighted output (log-weights not read);
 * islands from 2 particles (32768 islands, whose stage arrays live in
-  global memory) to 2048 (the block path), FP64/FP32/BF16 storage,
+  global memory) to 4096 (the block path; where a plane of an island spans
+  8 KB the mutation stages each source island in LDS), FP64/FP32/BF16 storage,
   multinomial and systematic within-island draws, Algorithms 6 and 7;
 * pf_run equals stepping, and its graph replay equals both, bit for bit;
 * a checkpoint taken between steps continues bit for bit.
@@ -39,6 +40,8 @@ CASES = [
     ("ar1-f32-M2-many", "ar1", 1 << 16, 2, "f32", "multinomial", True),
     ("lg4-f32-M2048-two", "lg4", 4096, 2048, "f32", "multinomial", True),
     ("lg8-f32-M2048-one-group-tiles", "lg8", 8192, 2048, "f32", "multinomial", True),
+    ("sv-f32-M4096", "sv", 1 << 14, 4096, "f32", "multinomial", True),
+    ("lg4-f64-M1024", "lg4", 8192, 1024, "f64", "multinomial", False),
 ]
 
 

@@ -121,3 +121,72 @@ int main() {
         shutil.rmtree(d, ignore_errors=True)
     cases, bad = int(out[0]), int(out[1])
     assert cases > 1_000_000 and bad == 0, (cases, bad)
+
+
+def test_padded_search_of_the_wide_group_path():
+    """The draw of the r > 64 tile path (padded_search), compiled for the host
+    from the kernel header: on a column whose member q sits at word
+    q + q / 64, it returns what a plain binary search over the unpadded
+    cumulative weights returns (the number of members <= target, at most
+    r - 1), for every radix 128 .. 4096, with ties, zero weights, targets
+    at and beyond the ends."""
+    import os
+    import re
+    import shutil
+    import subprocess
+    import tempfile
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ker = open(os.path.join(root, "paper_1812_01502_amd", "csrc", "pf_kernels.h")).read()
+    fn = re.search(r"template <int LR, typename T>\n__device__ __forceinline__ uint32_t padded_search\(.*?\n}\n",
+                   ker, re.S).group(0)
+    src = ("#define __device__\n#define __forceinline__ inline\n"
+           "#include <cstdint>\n#include <cstdio>\n#include <random>\n#include <vector>\n" + fn + r'''
+template <int LR> long check(std::mt19937& g, long& cases) {
+  const uint32_t r = 1u << LR;
+  long bad = 0;
+  std::vector<float> cdf(r), col(r + r / 64);
+  for (int trial = 0; trial < 200; ++trial) {
+    float acc = 0.f;
+    for (uint32_t q = 0; q < r; ++q) {
+      const uint32_t kind = g() % 8u;
+      acc += kind == 0 ? 0.f : (kind == 1 ? 1.f : (float)(g() % 1000u) * 1e-3f);
+      cdf[q] = acc;
+      col[q + q / 64] = acc;
+    }
+    for (int k = 0; k < 256; ++k) {
+      float t;
+      const uint32_t sel = g() % 4u;
+      if (sel == 0) t = cdf[g() % r];                   // exactly a cumulative weight
+      else if (sel == 1) t = acc * (float)(g() % 1000001u) * 1e-6f;
+      else if (sel == 2) t = -1.f;
+      else t = acc * 2.f + 1.f;
+      uint32_t pos = 0;
+      for (uint32_t s = r >> 1; s >= 1u; s >>= 1)
+        if (cdf[pos + s - 1u] <= t) pos += s;
+      ++cases;
+      if (padded_search<LR>(col.data(), t) != pos) ++bad;
+    }
+  }
+  return bad;
+}
+int main() {
+  std::mt19937 g(7);
+  long cases = 0, bad = 0;
+  bad += check<7>(g, cases); bad += check<8>(g, cases); bad += check<9>(g, cases);
+  bad += check<10>(g, cases); bad += check<11>(g, cases); bad += check<12>(g, cases);
+  printf("%ld %ld\n", cases, bad);
+  return 0;
+}
+''')
+    d = tempfile.mkdtemp()
+    try:
+        open(os.path.join(d, "s.cpp"), "w").write(src)
+        subprocess.run([cxx, "-O2", "-std=c++17", os.path.join(d, "s.cpp"), "-o", os.path.join(d, "s")], check=True)
+        out = subprocess.run([os.path.join(d, "s")], capture_output=True, text=True, check=True).stdout.split()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    cases, bad = int(out[0]), int(out[1])
+    assert cases == 6 * 200 * 256 and bad == 0
