@@ -653,7 +653,6 @@ struct LdsCarve {
 // LDS bytes of a tile kernel (must match the carve in pf_step_tile).
 __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint32_t r, uint32_t C,
                                                  uint32_t pad, int NT, bool blockpath, uint32_t xrow) {
-  const size_t E = (size_t)r * C;
   const size_t P = r + pad;
   const size_t PS = 4 + 3 * (size_t)D;
   size_t b = 0;
@@ -665,11 +664,8 @@ __host__ __device__ inline size_t tile_lds_bytes(int d, int D, size_t tsz, uint3
   add(red > C * tsz ? red : C * tsz);             // reduction scratch / carried weight
   add((size_t)(D > NT / 64 ? D : NT / 64) * tsz);  // tile reference point / wave maxima
   if (blockpath) {
-    add((E / 64) * tsz);  // chunk max
-    add((E / 64) * tsz);  // chunk sums
-    add(C * tsz);         // column max
-    add(C * tsz);         // column total
-    add(C * tsz);         // first member's uniform
+    add((size_t)(NT / 64) * tsz);  // wave maxima
+    add((size_t)(NT / 64) * tsz);  // wave sums
   }
   return b;
 }
@@ -919,6 +915,27 @@ __device__ __forceinline__ uint32_t padded_search(const T* col, T target) {
   return pp - pp / 65u;
 }
 
+// The draws of K consecutive members q0 .. q0 + K - 1 of a group of
+// r = 2^LR (cumulative weights in `col`, total `tot`): multinomial targets
+// u_q tot, systematic (q + U_0) tot / r; positions overwrite the uniforms
+// `us` word for word.
+template <int LR, int K, typename T>
+__device__ __forceinline__ void draw_run(const T* col, const T* us, int* pos, uint32_t q0, T tot, T u0,
+                                         bool sys) {
+  const T inv_r = (T)1 / (T)(1u << LR);  // exact: r is a power of two
+  T uu[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) uu[k] = us[k];
+  uint32_t pk[K];
+#pragma unroll
+  for (int k = 0; k < K; ++k) {
+    const T target = sys ? ((T)(q0 + (uint32_t)k) + u0) * tot * inv_r : uu[k] * tot;
+    pk[k] = padded_search<LR>(col, target);
+  }
+#pragma unroll
+  for (int k = 0; k < K; ++k) pos[k] = (int)pk[k];
+}
+
 template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
 __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const uint32_t tile,
                                                unsigned char* smem) {
@@ -927,7 +944,6 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   const int d = FULL ? D : (int)a.d;
   const uint32_t log2r = a.log2r, log2C = a.log2C;
   const uint32_t r = 1u << log2r, C = 1u << log2C;
-  const uint32_t E = r << log2C;
   const uint32_t P = r + a.pad;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   // word of group member q in its column of scl/scu/sca: for r > 64 one word
@@ -948,11 +964,8 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   T* red = reinterpret_cast<T*>(smem + lc.take(red_bytes > C * sizeof(T) ? red_bytes : C * sizeof(T)));
   T* colw = red;  // carried weights live where the reduction scratch was
   T* shx = reinterpret_cast<T*>(smem + lc.take((size_t)(D > NT / 64 ? D : NT / 64) * sizeof(T)));
-  T* chm = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
-  T* chs = reinterpret_cast<T*>(smem + lc.take((size_t)(E >> 6) * sizeof(T)));
-  T* colm = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
-  T* coltot = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
-  T* colu0 = reinterpret_cast<T*>(smem + lc.take((size_t)C * sizeof(T)));
+  T* chm = reinterpret_cast<T*>(smem + lc.take((size_t)(NT / 64) * sizeof(T)));  // wave maxima
+  T* chs = reinterpret_cast<T*>(smem + lc.take((size_t)(NT / 64) * sizeof(T)));  // wave sums
 
   const TileGeo geo = tile_geo(tile, log2r, a.log2R, log2C);
   const uint64_t N = a.N;
@@ -1064,65 +1077,77 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
       default: wave_groups<6, T, NT, PPT>(scl, scu, sca, colw, P, a.lnr, sys, wv, lane, tile_lwmax); break;
     }
   } else {
-    // r > 64: 64-member chunks, chunk maxima and sums through LDS
-    const uint32_t lg_nch = log2r - 6;
-    const uint32_t nch = 1u << lg_nch;
-    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
-      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      const T m = wave_max(scl[c * P + lix((ch << 6) + lane)]);
-      if (lane == 0) chm[task] = m;
+    // r > 64: thread t takes the K = 2 PPT consecutive members
+    // [K j, K j + K) of group c (G = r / K threads per group, t = c G + j).
+    // K divides 64, so those members are K consecutive words. A group's
+    // maximum and scan run within the thread, then over its lanes, then
+    // (G > 64) over its waves through LDS.
+    constexpr int K = 2 * PPT;
+    constexpr uint32_t LK = K == 2 ? 1u : (K == 4 ? 2u : (K == 8 ? 3u : 4u));
+    static_assert((1 << LK) == K && K <= 16, "members per thread");
+    const uint32_t lg_g = log2r - LK;
+    const uint32_t G = 1u << lg_g;
+    const uint32_t lgw = lg_g < 6u ? lg_g : 6u;      // the group's lanes within one wave
+    const uint32_t c = (uint32_t)tid >> lg_g, j = (uint32_t)tid & (G - 1u);
+    const uint32_t q0 = j << LK;
+    T* colp = scl + c * P;
+    const uint32_t w0 = lix(q0);
+    T v[K];
+    T mx = -INFINITY;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      v[k] = colp[w0 + k];
+      mx = fmaxT(mx, v[k]);
     }
-    __syncthreads();
-    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
-      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      // the group max over its (at most 64) chunk maxima, one per lane
-      const T m = wave_max((uint32_t)lane < nch ? chm[(c << lg_nch) + lane] : (T)-INFINITY);
-      const uint32_t qq = lix((ch << 6) + lane);
-      const T cdf = seg_scan(fexp(scl[c * P + qq] - m), 6u, (uint32_t)lane);
-      scl[c * P + qq] = cdf;
-      if (lane == 63) chs[task] = cdf;
-      if (ch == 0 && lane == 0) {
-        colm[c] = m;
-        colu0[c] = scu[c * P];  // first member's uniform, before positions overwrite it
-      }
+    mx = lgw == 6u ? wave_max(mx) : seg_max(mx, lgw, (uint32_t)lane);
+    const uint32_t nw = G >> 6;                       // waves per group (G > 64)
+    const uint32_t gw0 = nw ? ((uint32_t)wv / nw) * nw : 0u;
+    if (lg_g > 6u) {
+      if (lane == 0) chm[wv] = mx;
+      __syncthreads();
+      mx = wave_max((uint32_t)lane < nw ? chm[gw0 + lane] : (T)-INFINITY);
     }
-    __syncthreads();
-    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
-      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      // inclusive scan of the group's chunk totals, one per lane: the
-      // chunk's offset and the group total
-      const T cs = seg_scan((uint32_t)lane < nch ? chs[(c << lg_nch) + lane] : (T)0, 6u, (uint32_t)lane);
-      const T tot = lane_at(cs, nch - 1u);
-      const T offs = ch == 0u ? (T)0 : lane_at(cs, ch - 1u);
-      const uint32_t qq = lix((ch << 6) + lane);
-      scl[c * P + qq] += offs;
-      if (ch == 0) {
-        const T lw = colm[c] + flog_ge1(tot) - a.lnr;
-        tile_lwmax = fmaxT(tile_lwmax, lw);
-        if (lane == 0) {
-          coltot[c] = tot;
-          colw[c] = lw;
-        }
-      }
+    T run = 0;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      run += fexp(v[k] - mx);
+      v[k] = run;
     }
+    const uint32_t lq = (uint32_t)lane & ((1u << lgw) - 1u);
+    const T incl = seg_scan(run, lgw, lq);
+    T off = __shfl_up(incl, 1u, 64);
+    if (lq == 0u) off = 0;
+    T tot;
+    if (lg_g > 6u) {
+      if (lane == 63) chs[wv] = incl;
+      __syncthreads();
+      const T ws = seg_scan((uint32_t)lane < nw ? chs[gw0 + lane] : (T)0, 6u, (uint32_t)lane);
+      const uint32_t wi = (uint32_t)wv - gw0;
+      if (wi != 0u) off += lane_at(ws, wi - 1u);
+      tot = lane_at(ws, nw - 1u);
+    } else {
+      tot = lgw == 6u ? lane_at(incl, 63u) : __shfl(incl, (int)((uint32_t)lane | (G - 1u)), 64);
+    }
+#pragma unroll
+    for (int k = 0; k < K; ++k) colp[w0 + k] = v[k] + off;
+    if (j == 0u) {
+      const T lw = mx + flog_ge1(tot) - a.lnr;
+      tile_lwmax = lw;
+      colw[c] = lw;
+    }
+    // the systematic draw's U_0: the first member's uniform, read before
+    // any position overwrites it
+    const T u0 = sys ? scu[c * P] : (T)0;
     __syncthreads();
-    for (uint32_t task = wv; task < (E >> 6); task += NT / 64) {
-      const uint32_t c = task >> lg_nch, ch = task & (nch - 1u);
-      const uint32_t qq = (ch << 6) + lane;
-      const T tot = coltot[c];
-      const T u = scu[c * P + lix(qq)];
-      const T target = sys ? ((T)qq + colu0[c]) * tot / (T)r : u * tot;
-      const T* col = scl + c * P;
-      uint32_t pos;
-      switch (log2r) {
-        case 7: pos = padded_search<7>(col, target); break;
-        case 8: pos = padded_search<8>(col, target); break;
-        case 9: pos = padded_search<9>(col, target); break;
-        case 10: pos = padded_search<10>(col, target); break;
-        case 11: pos = padded_search<11>(col, target); break;
-        default: pos = padded_search<12>(col, target); break;
-      }
-      sca[c * P + lix(qq)] = (int)pos;
+    int* pos_out = sca + c * P + w0;
+    const T* us = scu + c * P + w0;
+    switch (log2r) {
+      case 7: draw_run<7, K>(colp, us, pos_out, q0, tot, u0, sys); break;
+      case 8: draw_run<8, K>(colp, us, pos_out, q0, tot, u0, sys); break;
+      case 9: draw_run<9, K>(colp, us, pos_out, q0, tot, u0, sys); break;
+      case 10: draw_run<10, K>(colp, us, pos_out, q0, tot, u0, sys); break;
+      case 11: draw_run<11, K>(colp, us, pos_out, q0, tot, u0, sys); break;
+      default: draw_run<12, K>(colp, us, pos_out, q0, tot, u0, sys); break;
     }
   }
   // the next step's offset: max of the new log-weights (deterministic), one
