@@ -376,7 +376,9 @@ def main():
               "bytes_per_particle_step": Bi,
               "hbm_frac_algorithmic": Bi * N / (iev / K) / 1e9 / HBM_PEAK_GBS,
               "speedup_over_global": (N * K / iwall) / gvalue,
-              "launches": "within-island tile kernel, island stages (one block), island gather"}
+              "launches": ("within-island tile kernel, island stages (" +
+                           ("blocks of 1024 islands, then one block" if N // Mi > 1024 else "one block") +
+                           "), island gather")}
 
     # -- ESS-gated stages with a rotating start (Sections 1.2 and 6.4) ----------
     theta = 0.5

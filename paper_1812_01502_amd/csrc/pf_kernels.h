@@ -1628,8 +1628,14 @@ struct IslandArgs {
   uint32_t m, log2m;
   uint32_t tau, sid, k0, k1;
   uint32_t no_swap;    // Algorithm 7 (else Algorithm 6)
-  uint32_t use_lds;    // the island arrays live in LDS ((sizeof(T) + 8) m bytes)
-  uint32_t uni_all;    // with use_lds: every stage's uniforms are drawn first (4 m log2m bytes more)
+  uint32_t use_lds;    // the island arrays live in LDS ((sizeof(T) + 8) mb bytes)
+  uint32_t uni_all;    // with use_lds: every stage's uniforms are drawn first (4 mb stages bytes more)
+  // the stages [s_begin, s_end) of islands [b mb, b mb + mb) in block b; the
+  // stages below log2 mb pair islands of one block only. from_prev: start
+  // from lv and src of the launch before (else from the island weights and
+  // the identity); the launch writes src, and lv when lv_out is set. One
+  // launch with mb = m runs everything.
+  uint32_t mb, s_begin, s_end, from_prev, lv_out;
 };
 
 // Uniform of island i at island stage s: word i mod 4 of the Philox block
@@ -1639,17 +1645,19 @@ __device__ __forceinline__ float island_uniform(const IslandArgs& ia, uint32_t i
   const uint32_t k = i & 3u;
   return word_uniform<float>(k == 0u ? w.w0 : k == 1u ? w.w1 : k == 2u ? w.w2 : w.w3);
 }
-// All four uniforms of Philox block q of stage s into us[4q .. 4q + 3] (< m).
-__device__ __forceinline__ void island_uniforms4(const IslandArgs& ia, uint32_t q, uint32_t s, float* us) {
+// All four uniforms of Philox block q of stage s (islands 4q .. 4q + 3, those
+// below m) into us[4q - base ..].
+__device__ __forceinline__ void island_uniforms4(const IslandArgs& ia, uint32_t q, uint32_t s, float* us,
+                                                 uint32_t base) {
   const Words w = philox(q, ia.tau, kIslandBlock + s, ia.sid, ia.k0, ia.k1);
-  const uint32_t i = q << 2;
-  us[i] = word_uniform<float>(w.w0);
-  if (i + 1u < ia.m) us[i + 1u] = word_uniform<float>(w.w1);
-  if (i + 2u < ia.m) us[i + 2u] = word_uniform<float>(w.w2);
-  if (i + 3u < ia.m) us[i + 3u] = word_uniform<float>(w.w3);
+  const uint32_t i = q << 2, l = i - base;
+  us[l] = word_uniform<float>(w.w0);
+  if (i + 1u < ia.m) us[l + 1u] = word_uniform<float>(w.w1);
+  if (i + 2u < ia.m) us[l + 2u] = word_uniform<float>(w.w2);
+  if (i + 3u < ia.m) us[l + 3u] = word_uniform<float>(w.w3);
 }
 
-// One block of 1024 threads. Stage s pairs island lo (bit s clear) with
+// A block of up to 1024 threads. Stage s pairs island lo (bit s clear) with
 // hi = lo + 2^s; each draws, with its own uniform, the island it holds next
 // with probability proportional to the pair's weights (members in index
 // order, first member whose cumulative weight exceeds the target), both then
@@ -1657,41 +1665,46 @@ __device__ __forceinline__ void island_uniforms4(const IslandArgs& ia, uint32_t 
 // samples keeps both in place. One thread owns a pair for the whole stage,
 // so a stage needs no synchronisation inside it; with the arrays in LDS the
 // uniforms are drawn first by all threads (four islands per Philox block),
-// for every stage at once when they fit.
+// for every stage of the launch at once when they fit. Many islands run in
+// two launches: the stages inside blocks of mb islands on m / mb blocks,
+// then the remaining stages on one block.
 template <typename T>
 __global__ void __launch_bounds__(1024) pf_island_draw(IslandArgs ia) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t m = ia.m, tid = threadIdx.x;
+  const uint32_t mb = ia.mb, tid = threadIdx.x, nth = blockDim.x;
+  const uint32_t base = blockIdx.x * mb;
   const bool in_lds = ia.use_lds != 0u;
   T* lv = in_lds ? reinterpret_cast<T*>(smem) : reinterpret_cast<T*>(ia.lv);
-  uint32_t* src = in_lds ? reinterpret_cast<uint32_t*>(smem + (size_t)m * sizeof(T)) : ia.src;
-  float* us = reinterpret_cast<float*>(smem + (size_t)m * (sizeof(T) + 4));
-  const T* w = reinterpret_cast<const T*>(ia.isl_lw);
-  for (uint32_t i = tid; i < m; i += 1024u) {
-    lv[i] = w[i];
-    src[i] = i;
+  uint32_t* src = in_lds ? reinterpret_cast<uint32_t*>(smem + (size_t)mb * sizeof(T)) : ia.src;
+  float* us = reinterpret_cast<float*>(smem + (size_t)mb * (sizeof(T) + 4));
+  const T* w = reinterpret_cast<const T*>(ia.from_prev ? ia.lv : ia.isl_lw);
+  for (uint32_t i = tid; i < mb; i += nth) {
+    lv[i] = w[base + i];
+    src[i] = ia.from_prev ? ia.src[base + i] : base + i;
   }
   __syncthreads();
   const T ln2 = (T)0.6931471805599453;
-  const uint32_t nq = (m + 3u) >> 2;
+  // Philox blocks of this block's islands: q0 .. q0 + nq - 1 (four islands each)
+  const uint32_t q0 = base >> 2, nq = (mb + 3u) >> 2;
+  const uint32_t nst = ia.s_end - ia.s_begin;
   const bool all = in_lds && ia.uni_all != 0u;
   if (all) {
     // every stage's uniforms at once: independent Philox blocks for all threads
-    for (uint32_t wq = tid; wq < nq * ia.log2m; wq += 1024u)
-      island_uniforms4(ia, wq % nq, wq / nq, us + (size_t)(wq / nq) * m);
+    for (uint32_t wq = tid; wq < nq * nst; wq += nth)
+      island_uniforms4(ia, q0 + wq % nq, ia.s_begin + wq / nq, us + (size_t)(wq / nq) * mb, base);
     __syncthreads();
   }
-  for (uint32_t s = 0; s < ia.log2m; ++s) {
+  for (uint32_t s = ia.s_begin; s < ia.s_end; ++s) {
     const uint32_t bit = 1u << s;
     if (in_lds && !all) {
-      for (uint32_t q = tid; q < nq; q += 1024u) island_uniforms4(ia, q, s, us);
+      for (uint32_t q = tid; q < nq; q += nth) island_uniforms4(ia, q0 + q, s, us, base);
       __syncthreads();
     }
-    const float* ust = all ? us + (size_t)s * m : us;
-    for (uint32_t p = tid; p < (m >> 1); p += 1024u) {
+    const float* ust = all ? us + (size_t)(s - ia.s_begin) * mb : us;
+    for (uint32_t p = tid; p < (mb >> 1); p += nth) {
       const uint32_t lo = ((p >> s) << (s + 1)) | (p & (bit - 1u)), hi = lo | bit;
-      const float ulo = in_lds ? ust[lo] : island_uniform(ia, lo, s);
-      const float uhi = in_lds ? ust[hi] : island_uniform(ia, hi, s);
+      const float ulo = in_lds ? ust[lo] : island_uniform(ia, base + lo, s);
+      const float uhi = in_lds ? ust[hi] : island_uniform(ia, base + hi, s);
       const T vlo = lv[lo], vhi = lv[hi];
       const T mx = fmaxT(vlo, vhi);
       const T clo = fexp(vlo - mx), tot = clo + fexp(vhi - mx);
@@ -1710,8 +1723,13 @@ __global__ void __launch_bounds__(1024) pf_island_draw(IslandArgs ia) {
     }
     __syncthreads();
   }
-  if (in_lds)
-    for (uint32_t i = tid; i < m; i += 1024u) ia.src[i] = src[i];
+  if (in_lds) {
+    T* lvo = reinterpret_cast<T*>(ia.lv);
+    for (uint32_t i = tid; i < mb; i += nth) {
+      ia.src[base + i] = src[i];
+      if (ia.lv_out) lvo[base + i] = lv[i];
+    }
+  }
 }
 
 // Destination particle kM + j copies particle isl_anc[src[k] M + j] (the

@@ -205,7 +205,7 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       auto k = pf_island_draw<T>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, dim3(1), dim3(1024), rq.lds, st, *rq.ia);
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(rq.nt), rq.lds, st, *rq.ia);
       return hipGetLastError();
     }
     case LW_ISLAND_GATHER: {

@@ -279,16 +279,52 @@ pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev)
   ia.k1 = a.k1;
   ia.no_swap = h->island_no_swap ? 1u : 0u;
   ia.use_lds = (size_t)m * (h->tsz + 8) <= kIslandLdsBytes ? 1u : 0u;
-  ia.uni_all = (size_t)m * (h->tsz + 4 + 4 * (size_t)h->log2m) <= kIslandLdsBytes ? 1u : 0u;
+  // LDS of a launch over blocks of mb islands running nst stages
+  auto draw_lds = [&](IslandArgs& x, uint32_t mb, uint32_t nst) {
+    x.uni_all = (size_t)mb * (h->tsz + 4 + 4 * (size_t)nst) <= kIslandLdsBytes ? 1u : 0u;
+    return !x.use_lds ? (size_t)0 : (size_t)mb * (h->tsz + 4 + (x.uni_all ? 4 * (size_t)nst : 4));
+  };
   LaunchReq rd{};
   rd.what = LW_ISLAND_DRAW;
   rd.D = h->D;
   rd.mk = h->mk;
-  rd.grid = 1;
-  rd.lds = !ia.use_lds ? 0 : (size_t)m * (h->tsz + 4 + (ia.uni_all ? 4 * (size_t)h->log2m : 4));
-  rd.ia = &ia;
-  e = launch(h, rd, &a);
-  if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
+  constexpr uint32_t kLgBlockIslands = 10;
+  if (ia.use_lds && h->log2m > kLgBlockIslands) {
+    // the first stages inside blocks of 1024 islands, one block each (one
+    // pair per thread), then the rest on one block
+    IslandArgs p1 = ia;
+    p1.mb = 1u << kLgBlockIslands;
+    p1.s_begin = 0;
+    p1.s_end = kLgBlockIslands;
+    p1.lv_out = 1;
+    rd.grid = m >> kLgBlockIslands;
+    rd.nt = 512;
+    rd.lds = draw_lds(p1, p1.mb, kLgBlockIslands);
+    rd.ia = &p1;
+    e = launch(h, rd, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
+    IslandArgs p2 = ia;
+    p2.mb = m;
+    p2.s_begin = kLgBlockIslands;
+    p2.s_end = h->log2m;
+    p2.from_prev = 1;
+    rd.grid = 1;
+    rd.nt = 1024;
+    rd.lds = draw_lds(p2, m, h->log2m - kLgBlockIslands);
+    rd.ia = &p2;
+    e = launch(h, rd, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
+  } else {
+    ia.mb = m;
+    ia.s_begin = 0;
+    ia.s_end = h->log2m;
+    rd.grid = 1;
+    rd.nt = 1024;
+    rd.lds = draw_lds(ia, m, h->log2m);
+    rd.ia = &ia;
+    e = launch(h, rd, &a);
+    if (e != hipSuccess) return hip_fail(h, e, "island stage launch");
+  }
 
   StepArgs<T, S> g = a;
   g.anc = h->anc;

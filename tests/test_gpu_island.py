@@ -6,9 +6,10 @@ oracle, through the C-ABI.
   log-normaliser agree (where every draw involved clears the margin); the
   output is unweighted; a second step continues from the device's own
   unweighted output (log-weights not read);
-* island stages with every stage's uniforms in LDS, one stage's at a time
-  (4096 islands), and the stage arrays in global memory (2^15 and 2^17
-  islands);
+* island stages with every stage's uniforms in LDS, one stage's at a time,
+  in two launches (more than 1024 islands in LDS: the first ten stages in
+  blocks of 1024 islands, then the rest; 2048 and 4096 islands), and with
+  the stage arrays in global memory (2^15 and 2^17 islands);
 * islands from 2 particles (32768 islands, whose stage arrays live in
   global memory) to 4096 (the block path; where a plane of an island spans
   8 KB the mutation stages each source island in LDS), FP64/FP32/BF16 storage,
@@ -46,6 +47,8 @@ CASES = [
     ("sv-f32-M4096", "sv", 1 << 14, 4096, "f32", "multinomial", True),
     ("ar1-f32-M8-m4096", "ar1", 1 << 15, 8, "f32", "multinomial", True),
     ("ar1-f32-M2-m131072", "ar1", 1 << 18, 2, "f32", "multinomial", True),
+    ("sv-f32-M16-m2048", "sv", 1 << 15, 16, "f32", "multinomial", True),
+    ("ar1-f64-M4-m4096-alg6-sys", "ar1", 1 << 14, 4, "f64", "systematic", False),
     ("lg4-f64-M1024", "lg4", 8192, 1024, "f64", "multinomial", False),
 ]
 
