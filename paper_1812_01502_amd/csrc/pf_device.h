@@ -158,8 +158,10 @@ template <> __device__ __forceinline__ double word_uniform<double>(uint32_t w) {
 __device__ __forceinline__ void box_muller(uint32_t wa, uint32_t wb, float& zc, float& zs) {
   const float u1 = (float)((wa >> 8) + 1u) * 0x1p-24f;
   const float u2 = (float)(wb >> 8) * 0x1p-24f;
-  // -2 ln u1 = -2 ln(2) log2(u1)
-  const float rho = __builtin_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
+  // -2 ln u1 = -2 ln(2) log2(u1), at least about 1.2e-7 (never denormal), so
+  // the hardware square root (1 ulp) needs none of the scaling and
+  // correction steps of the correctly rounded one
+  const float rho = __builtin_amdgcn_sqrtf(-1.3862943611198906f * __builtin_amdgcn_logf(u1));
   // the hardware sin/cos take their argument in revolutions: sin(2 pi u2)
   zc = rho * __builtin_amdgcn_cosf(u2);
   zs = rho * __builtin_amdgcn_sinf(u2);
