@@ -8,14 +8,18 @@
 //   phase B  per group (a column of the tile): max, exp, inclusive scan,
 //            carried weight m_G + ln c_{r-1} - ln r, inverse-CDF draw.
 //            r <= 64: one wave segment per group (DPP row operations and
-//            cross-lane permutes, two groups per wave at a time);
-//            r > 64: 64-member chunks with LDS chunk prefixes.
-//   phase C  remaining normals, gather of the ancestor from LDS,
+//            cross-lane permutes; up to four 64-lane tasks interleaved);
+//            r > 64: runs of consecutive members per thread, scanned in
+//            registers, then over lanes, then over waves through LDS; a
+//            radix-specialised binary search on a bank-padded column.
+//   phase C  gather of the ancestor from LDS, the normals (drawn in phase A
+//            already for one pair per thread and 4 to 8 dimensions),
 //            propagation, coalesced store of x and the new log-weight.
-// Block 0 of every step kernel is not a tile: it reduces the previous
-// step's tile partials (estimate record, log-normaliser) while the tiles
-// run. The offset subtracted from the stored log-weights at the next load
-// (their maximum) is gathered with an order-preserving integer atomicMax.
+// The tile partials (estimate record, log-normaliser) are reduced later, a
+// few steps at a time (pf_finalize_multi). Block 0 of a step records the
+// offset that the step subtracts and clears the slots of a later one. The
+// offset subtracted from the stored log-weights at the next load (their
+// maximum) is gathered with an order-preserving integer atomicMax.
 // Global path (r >= N): weight + tile scan, grid prefix, draw + gather +
 // propagate.
 #pragma once
