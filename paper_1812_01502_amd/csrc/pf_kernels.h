@@ -1768,21 +1768,26 @@ __global__ void __launch_bounds__(256) pf_island_gather(StepArgs<T, S> a) {
 }
 
 // The same mutation with one block per destination island k, for islands
-// whose states fit in LDS (d M values): the source island src[k] is staged
-// with coalesced loads, then every ancestor is read from LDS instead of by a
-// scattered global load. Results are those of pf_island_gather.
+// of M = 1024 PG particles whose states fit in LDS (d M values): the source
+// island src[k] is staged with coalesced loads; while they are in flight
+// each thread reads the ancestors of its PG pairs and draws their normals
+// (none of which depends on the states); then every ancestor is read from
+// LDS instead of by a scattered global load. Results are those of
+// pf_island_gather.
 constexpr int kIslandGatherNT = 512;
-template <int D, int MK, typename T, typename S>
+template <int D, int MK, typename T, typename S, int PG>
 __global__ void __launch_bounds__(kIslandGatherNT) pf_island_gather_lds(StepArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   T* xs = reinterpret_cast<T*>(smem);  // [j][member]
+  constexpr uint32_t M = 2u * kIslandGatherNT * PG;
   const int d = (int)a.d;
   const uint64_t N = a.N;
   const uint32_t tau = a.t + 1u;
-  const uint32_t M = 1u << a.log2M, half = M >> 1;
-  const uint64_t sbase = (uint64_t)a.isl_src[blockIdx.x] << a.log2M;
-  const uint64_t dbase = (uint64_t)blockIdx.x << a.log2M;
-  for (uint32_t q = threadIdx.x; q < half; q += kIslandGatherNT) {
+  const uint64_t sbase = (uint64_t)a.isl_src[blockIdx.x] * M;
+  const uint64_t dbase = (uint64_t)blockIdx.x * M;
+#pragma unroll
+  for (int g = 0; g < PG; ++g) {
+    const uint32_t q = threadIdx.x + (uint32_t)g * kIslandGatherNT;
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       if (j < d) {
@@ -1793,24 +1798,33 @@ __global__ void __launch_bounds__(kIslandGatherNT) pf_island_gather_lds(StepArgs
       }
     }
   }
+  uint2 aa[PG];
+  T z[PG][2][D];
+#pragma unroll
+  for (int g = 0; g < PG; ++g) {
+    const uint32_t q = threadIdx.x + (uint32_t)g * kIslandGatherNT;
+    aa[g] = *reinterpret_cast<const uint2*>(a.isl_anc + sbase + 2u * q);
+#pragma unroll
+    for (int j = 0; j < D; ++j) z[g][0][j] = z[g][1][j] = 0;
+    T u0, u1;
+    pair_randoms<D, T>((uint32_t)((dbase >> 1) + q), tau, a.sid, a.k0, a.k1, d, u0, u1, z[g][0], z[g][1]);
+  }
   __syncthreads();
-  for (uint32_t q = threadIdx.x; q < half; q += kIslandGatherNT) {
+#pragma unroll
+  for (int g = 0; g < PG; ++g) {
+    const uint32_t q = threadIdx.x + (uint32_t)g * kIslandGatherNT;
     const uint64_t i0 = dbase + 2u * q;
-    const uint2 aa = *reinterpret_cast<const uint2*>(a.isl_anc + sbase + 2u * q);
-    if (a.anc) *reinterpret_cast<uint2*>(a.anc + i0) = aa;
+    if (a.anc) *reinterpret_cast<uint2*>(a.anc + i0) = aa[g];
     // ancestors of a within-island draw lie in the source island
-    const uint32_t l0 = (uint32_t)(aa.x - sbase), l1 = (uint32_t)(aa.y - sbase);
-    T xh[2][D], z[2][D], xo[2][D];
+    const uint32_t l0 = (uint32_t)(aa[g].x - sbase), l1 = (uint32_t)(aa[g].y - sbase);
+    T xh[2][D], xo[2][D];
 #pragma unroll
     for (int j = 0; j < D; ++j) {
       xh[0][j] = (j < d) ? xs[(size_t)j * M + l0] : (T)0;
       xh[1][j] = (j < d) ? xs[(size_t)j * M + l1] : (T)0;
-      z[0][j] = z[1][j] = 0;
     }
-    T u0, u1;
-    pair_randoms<D, T>((uint32_t)(i0 >> 1), tau, a.sid, a.k0, a.k1, d, u0, u1, z[0], z[1]);
-    Model<D, MK, T>::propagate(a.mp, xh[0], z[0], xo[0]);
-    Model<D, MK, T>::propagate(a.mp, xh[1], z[1], xo[1]);
+    Model<D, MK, T>::propagate(a.mp, xh[0], z[g][0], xo[0]);
+    Model<D, MK, T>::propagate(a.mp, xh[1], z[g][1], xo[1]);
 #pragma unroll
     for (int j = 0; j < D; ++j)
       if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + i0, xo[0][j], xo[1][j]);

@@ -211,7 +211,10 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
     case LW_ISLAND_GATHER: {
       if (rq.lds > 0) {
         // one block per destination island, its source island staged in LDS
-        auto k = pf_island_gather_lds<D, MK, T, S>;
+        // (islands of 1024 ppt particles)
+        auto k = rq.ppt == 1 ? pf_island_gather_lds<D, MK, T, S, 1>
+                             : (rq.ppt == 2 ? pf_island_gather_lds<D, MK, T, S, 2> : pf_island_gather_lds<D, MK, T, S, 4>);
+        if (rq.ppt != 1 && rq.ppt != 2 && rq.ppt != 4) return hipErrorInvalidValue;
         hipError_t e = ensure_lds(k, rq.lds);
         if (e != hipSuccess) return e;
         hipLaunchKernelGGL(k, dim3(rq.grid), dim3(kIslandGatherNT), rq.lds, st, a);

@@ -335,14 +335,16 @@ pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev)
   rg.what = LW_ISLAND_GATHER;
   rg.D = h->D;
   rg.mk = h->mk;
-  // one block per destination island when the source island's states fit
-  // in LDS and a plane of it spans at least 8 KB: below that the scattered
-  // loads of the plain gather stay within few cache lines per wave and it
-  // is the faster one (LG-8 with islands of 1024: 18.7 against 21.1 us; SV
-  // with islands of 4096: 63.8 against 29.8 us)
+  // one block per destination island when the island has 1024, 2048 or
+  // 4096 particles, its states fit in LDS and a plane of it spans at least
+  // 8 KB: below that the scattered loads of the plain gather stay within few
+  // cache lines per wave and it is the faster one (LG-8 with islands of
+  // 1024: 18.7 against 19.9 us; SV with islands of 4096: 63.8 against 24.2)
   const size_t island_vals = (size_t)h->d << h->log2M;
-  if (h->log2M >= 10 && ((size_t)h->tsz << h->log2M) >= 8192u && island_vals * h->tsz <= kIslandGatherLds) {
+  if (h->log2M >= 10 && h->log2M <= 12 && ((size_t)h->tsz << h->log2M) >= 8192u &&
+      island_vals * h->tsz <= kIslandGatherLds) {
     rg.grid = m;
+    rg.ppt = 1 << (h->log2M - 10);
     rg.lds = island_vals * h->tsz;
   } else {
     const uint64_t blocks = (h->N / 2 + 255) / 256;

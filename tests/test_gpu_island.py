@@ -11,8 +11,9 @@ oracle, through the C-ABI.
   blocks of 1024 islands, then the rest; 2048 and 4096 islands), and with
   the stage arrays in global memory (2^15 and 2^17 islands);
 * islands from 2 particles (32768 islands, whose stage arrays live in
-  global memory) to 4096 (the block path; where a plane of an island spans
-  8 KB the mutation stages each source island in LDS), FP64/FP32/BF16 storage,
+  global memory) to 4096 (the block path; islands of 1024 to 4096 whose
+  plane spans 8 KB stage each source island in LDS for the mutation, one to
+  four pairs per thread), FP64/FP32/BF16 storage,
   multinomial and systematic within-island draws, Algorithms 6 and 7;
 * pf_run equals stepping, and its graph replay equals both, bit for bit;
 * a checkpoint taken between steps continues bit for bit.
