@@ -683,6 +683,10 @@ pf_status plan_stages(pf_handle* h) {
       } else if (512u * pb >= 2u * sp.r && 512u * pb <= N) {
         sp.nt = 256;
         sp.ppt = (int)pb;
+      } else if (h->island && sp.log2R == 0 && sp.r <= 1024 && 512u * pb >= sp.r && 512u * pb <= N) {
+        // the within-island launch: one island per 256-thread tile
+        sp.nt = 256;
+        sp.ppt = (int)pb;
       } else if (sp.r <= 1024 && N >= 2048) {
         sp.nt = 1024;
         sp.ppt = 1;
