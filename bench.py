@@ -30,7 +30,9 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
-PROFILE_SUMMARY = os.path.join(ROOT, "profiles", "pf_step_tile_lg8_n2p20_r64.json")
+# rocprofv3 counter summaries of the step kernel, per workload
+PROFILE_SUMMARY = {"lg8": os.path.join(ROOT, "profiles", "pf_step_tile_lg8_n2p20_r64.json"),
+                   "sv": os.path.join(ROOT, "profiles", "pf_step_tile_sv_n2p24_r64.json")}
 KERNEL_SOURCES = ["paper_1812_01502_amd/csrc/pf_kernels.h", "paper_1812_01502_amd/csrc/pf_device.h"]
 
 
@@ -330,7 +332,8 @@ def main():
     launch_bytes = B * N
     avg_launch_s = ev_s / K                            # one step kernel per step
     achieved = launch_bytes / avg_launch_s / 1e9
-    traffic = load_traffic(PROFILE_SUMMARY, launch_bytes)
+    # the counters were taken at the workload's own N only
+    traffic = load_traffic(PROFILE_SUMMARY[args.workload], launch_bytes) if N == cfg["N"] else None
 
     # -- global bootstrap filter (r = N) ---------------------------------------
     g = make(N)
