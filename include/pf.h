@@ -325,6 +325,28 @@ pf_status pf_batch_sync(pf_batch* b);
  * pf_batch_create of this thread. */
 const char* pf_batch_last_error(const pf_batch* b);
 
+/* Device memory of handles and batches. By default every device buffer of a
+ * handle or batch (state planes, log-weights, reduction records, control
+ * block, estimate records, scratch of the global and island paths) comes
+ * from hipMalloc and goes back with hipFree. pf_set_allocator installs a
+ * pair of callbacks instead, e.g. a framework's caching allocator:
+ *   alloc(bytes, ctx) returns device memory on the current device of at
+ *   least `bytes` bytes, aligned to 256 bytes, or NULL when it has none;
+ *   free_(ptr, ctx) takes back a pointer alloc returned.
+ * Process-wide and thread-safe. The setting applies to handles and batches
+ * created afterwards; each keeps the allocator it was created with and frees
+ * every buffer with it (pf_destroy / pf_batch_destroy, or a failed create,
+ * after synchronising its stream). alloc = free_ = NULL restores
+ * hipMalloc/hipFree. The callbacks are called only from pf_create and
+ * pf_batch_create (alloc) and from pf_destroy, pf_batch_destroy and failed
+ * creates (free_), on the calling thread; they must stay valid until every
+ * handle using them is destroyed.
+ * Errors: PF_E_INVALID when exactly one of alloc and free_ is NULL. A NULL
+ * from alloc makes the create fail with PF_E_OOM, a misaligned pointer with
+ * PF_E_INVALID (the pointer is handed back to free_ first). */
+pf_status pf_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx),
+                           void* ctx);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

@@ -12,13 +12,15 @@ r) per time step, the stage rotating with the step.
 """
 from __future__ import annotations
 
+import atexit
 import ctypes
+import weakref
 
 import numpy as np
 
 from . import _lib as L
 
-__all__ = ["Filter", "BatchFilter", "PfError", "load_library", "DTYPES", "RESAMPLERS"]
+__all__ = ["Filter", "BatchFilter", "PfError", "load_library", "set_allocator", "DTYPES", "RESAMPLERS"]
 
 DTYPES = {"f32": L.PF_DTYPE_F32, "bf16": L.PF_DTYPE_BF16, "f64": L.PF_DTYPE_F64}
 RESAMPLERS = {"multinomial": L.PF_RESAMPLE_MULTINOMIAL, "systematic": L.PF_RESAMPLE_SYSTEMATIC}
@@ -40,6 +42,87 @@ class PfError(RuntimeError):
 
 def load_library():
     return L.load()
+
+
+# The device allocator of filters created from now on (pf_set_allocator):
+# None until the first filter is created or set_allocator is called.
+_allocator = {"kind": None, "fns": None}
+
+
+def set_allocator(kind: str = "torch", alloc=None, free=None):
+    """Choose where the device buffers of filters and batches created from now
+    on come from: ``"torch"`` (``torch.cuda``'s caching allocator, on the
+    current device and stream), ``"hip"`` (``hipMalloc``/``hipFree`` inside
+    the library) or ``"custom"`` with Python callables ``alloc(nbytes) ->
+    int device pointer (or None)`` and ``free(ptr)``. Existing filters keep
+    the allocator they were created with. The callbacks stay referenced here,
+    so they outlive every filter that uses them."""
+    lib = L.load()
+    if kind == "hip":
+        st = lib.pf_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None)
+        fns = None
+    else:
+        if kind == "torch":
+            import torch
+
+            def alloc(nbytes):
+                return torch.cuda.caching_allocator_alloc(int(nbytes))
+
+            def free(ptr):
+                torch.cuda.caching_allocator_delete(int(ptr))
+        elif kind != "custom" or alloc is None or free is None:
+            raise ValueError("set_allocator: kind is 'torch', 'hip' or 'custom' (with alloc and free)")
+        user_alloc, user_free = alloc, free
+
+        def c_alloc(nbytes, _ctx):
+            try:
+                p = user_alloc(int(nbytes))
+            except Exception:   # out of memory: the create reports PF_E_OOM
+                return None
+            return int(p) if p else None
+
+        def c_free(ptr, _ctx):
+            try:
+                user_free(int(ptr))
+            except Exception as e:  # cannot propagate through the C caller
+                import sys
+                print(f"paper_1812_01502_amd: allocator free failed: {e}", file=sys.stderr)
+
+        fns = (L.ALLOC_FN(c_alloc), L.FREE_FN(c_free))
+        st = lib.pf_set_allocator(fns[0], fns[1], None)
+    if st != L.PF_OK:
+        raise PfError(st, "pf_set_allocator")
+    if _allocator["fns"] is not None:
+        # filters created with the previous callbacks may still hold them
+        _allocator.setdefault("retired", []).append(_allocator["fns"])
+    _allocator.update(kind=kind, fns=fns)
+
+
+# Live filters and batches: closed at interpreter exit, before torch (whose
+# allocator may own their memory) is torn down.
+_live = weakref.WeakSet()
+
+
+def _close_live():
+    for obj in list(_live):
+        try:
+            obj.close()
+        except Exception:
+            pass
+
+
+def _default_allocator():
+    """First filter of the process: device memory from torch's caching
+    allocator when torch has a GPU, else from hipMalloc."""
+    if _allocator["kind"] is not None:
+        return
+    atexit.register(_close_live)   # after torch's import: runs before torch's own exit hooks
+    try:
+        import torch
+        use_torch = torch.cuda.is_available()
+    except ImportError:
+        use_torch = False
+    set_allocator("torch" if use_torch else "hip")
 
 
 def _dptr(a):
@@ -85,6 +168,7 @@ class Filter:
                  keep_ancestors: bool = False, stream: int | None = None, full_cycle: bool = False,
                  island: int = 0, island_swap: bool = False, ess_threshold: float = 0.0):
         self._lib = L.load()
+        _default_allocator()
         self.d = int(model.d)
         self.n = int(n)
         self.dtype = dtype
@@ -109,6 +193,7 @@ class Filter:
         if st != L.PF_OK:
             raise PfError(st, self._lib.pf_last_error(None).decode())
         self._h = h
+        _live.add(self)
         self._x_dtype = {"f32": np.float32, "bf16": np.uint16, "f64": np.float64}[dtype]
         self._w_dtype = np.float64 if dtype == "f64" else np.float32
 
@@ -242,6 +327,7 @@ class BatchFilter:
     def __init__(self, models, ns, radices, seeds, stream_ids=None, resampler: str = "multinomial",
                  stream: int | None = None):
         self._lib = L.load()
+        _default_allocator()
         n = len(models)
         self.n = n
         self.ds = [int(m.d) for m in models]
@@ -267,6 +353,7 @@ class BatchFilter:
         if st != L.PF_OK:
             raise PfError(st, self._lib.pf_batch_last_error(None).decode())
         self._h = h
+        _live.add(self)
 
     def _check(self, st):
         if st != L.PF_OK:

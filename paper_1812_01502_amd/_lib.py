@@ -25,9 +25,13 @@ EXPORTS = ("pf_create", "pf_destroy", "pf_reset", "pf_step", "pf_run", "pf_estim
            "pf_sync", "pf_status_string", "pf_last_error", "pf_save", "pf_load",
            "pf_batch_create", "pf_batch_destroy", "pf_batch_step", "pf_batch_run",
            "pf_batch_estimates", "pf_batch_filter_info", "pf_batch_tuning", "pf_batch_get_state",
-           "pf_batch_set_state", "pf_batch_reset", "pf_batch_sync", "pf_batch_last_error")
+           "pf_batch_set_state", "pf_batch_reset", "pf_batch_sync", "pf_batch_last_error",
+           "pf_set_allocator")
 
 DPTR = POINTER(c_double)
+# pf_set_allocator callbacks: alloc(bytes, ctx) -> device pointer, free_(ptr, ctx)
+ALLOC_FN = ctypes.CFUNCTYPE(c_void_p, ctypes.c_size_t, c_void_p)
+FREE_FN = ctypes.CFUNCTYPE(None, c_void_p, c_void_p)
 
 
 class PfModel(ctypes.Structure):
@@ -107,6 +111,7 @@ def load():
         "pf_batch_reset": (c_int32, [H, c_uint32, c_uint64, c_uint32]),
         "pf_batch_sync": (c_int32, [H]),
         "pf_batch_last_error": (c_char_p, [H]),
+        "pf_set_allocator": (c_int32, [ALLOC_FN, FREE_FN, c_void_p]),
         "pf_status_string": (c_char_p, [c_int32]),
         "pf_last_error": (c_char_p, [H]),
     }

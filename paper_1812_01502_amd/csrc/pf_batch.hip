@@ -70,6 +70,7 @@ struct pf_batch {
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
   std::string err;
+  DevAllocator dalloc_fn;  // the allocator current at create time
   std::vector<void*> allocs;
 };
 
@@ -91,19 +92,18 @@ pf_status bhip(pf_batch* b, hipError_t e, const char* what) {
 
 pf_status balloc(pf_batch* b, void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return bfail(b, PF_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
+  hipError_t e = dev_alloc(b->dalloc_fn, p, bytes);
+  if (e == hipErrorInvalidValue)
+    return bfail(b, PF_E_INVALID, "the installed allocator returned a pointer not aligned to 256 bytes");
+  if (e != hipSuccess)
+    return bfail(b, PF_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   b->allocs.push_back(*p);
   b->bytes += bytes;
   return PF_OK;
 }
 
 void brelease(pf_batch* b) {
-  for (void* p : b->allocs) (void)hipFree(p);
+  for (void* p : b->allocs) dev_free(b->dalloc_fn, p);
   b->allocs.clear();
 }
 
@@ -369,6 +369,7 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
   pf_batch* b = new (std::nothrow) pf_batch();
   if (!b) return bfail(nullptr, PF_E_OOM, "host allocation failed");
   b->stream = reinterpret_cast<hipStream_t>(hip_stream);
+  b->dalloc_fn = current_allocator();
   b->n = n;
   b->fh.resize(n);
   auto bail = [&](pf_status s) {

@@ -19,6 +19,50 @@ namespace pfh {
 
 using namespace pfk;
 
+// Device memory of handles and batches: hipMalloc/hipFree, or the callbacks
+// installed by pf_set_allocator. A handle or batch keeps the allocator that
+// was current when it was created and frees every buffer with it.
+struct DevAllocator {
+  void* (*alloc)(size_t, void*) = nullptr;  // nullptr: hipMalloc
+  void (*free_)(void*, void*) = nullptr;
+  void* ctx = nullptr;
+};
+// The allocator pf_set_allocator installed (defined in pf_runtime.hip).
+DevAllocator current_allocator();
+// Pointers handed out by an allocator callback must be aligned to this many
+// bytes (vector loads of the state planes, 64-bit atomics of the control
+// block).
+constexpr uintptr_t kAllocAlign = 256;
+
+// Allocate `bytes` (at least 16) of device memory with `a`. Returns
+// hipSuccess, or hipErrorOutOfMemory when the allocator gave nothing,
+// hipErrorInvalidValue when it gave a misaligned pointer (which is then
+// returned to it).
+inline hipError_t dev_alloc(const DevAllocator& a, void** p, size_t bytes) {
+  if (bytes == 0) bytes = 16;
+  if (!a.alloc) {
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) {
+      *p = nullptr;
+      (void)hipGetLastError();
+    }
+    return e;
+  }
+  *p = a.alloc(bytes, a.ctx);
+  if (!*p) return hipErrorOutOfMemory;
+  if ((reinterpret_cast<uintptr_t>(*p) & (kAllocAlign - 1)) != 0) {
+    a.free_(*p, a.ctx);
+    *p = nullptr;
+    return hipErrorInvalidValue;
+  }
+  return hipSuccess;
+}
+inline void dev_free(const DevAllocator& a, void* p) {
+  if (!p) return;
+  if (a.free_) a.free_(p, a.ctx);
+  else (void)hipFree(p);
+}
+
 // Row pitch of a tile's staged states in LDS: at strides below the tile
 // width consecutive particles fall in consecutive rows, so an odd pitch keeps
 // their writes in different banks; wider strides write along rows.

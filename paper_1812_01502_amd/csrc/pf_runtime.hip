@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
 #include <type_traits>
@@ -20,7 +21,18 @@ namespace {
 
 thread_local std::string g_create_error;
 
+// The allocator of handles and batches created from now on (pf_set_allocator).
+std::mutex g_alloc_mu;
+DevAllocator g_alloc;
+
 }  // namespace
+
+namespace pfh {
+DevAllocator current_allocator() {
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  return g_alloc;
+}
+}  // namespace pfh
 
 struct pf_handle {
   int kind = 0, d = 0, D = 1, mk = 0;
@@ -74,10 +86,14 @@ struct pf_handle {
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
   std::string err;
+  DevAllocator dalloc_fn;    // the allocator current at create time
   std::vector<void*> allocs;
 };
 
 namespace {
+
+// Most stages of a plan (radix 2 at N = 2^30 has 30).
+constexpr uint32_t kMaxStages = 32;
 
 pf_status fail(pf_handle* h, pf_status s, const std::string& msg) {
   if (h) {
@@ -96,12 +112,11 @@ pf_status hip_fail(pf_handle* h, hipError_t e, const char* what) {
 
 pf_status dalloc(pf_handle* h, void** p, size_t bytes) {
   if (bytes == 0) bytes = 16;
-  hipError_t e = hipMalloc(p, bytes);
-  if (e != hipSuccess) {
-    *p = nullptr;
-    (void)hipGetLastError();
-    return fail(h, PF_E_OOM, "hipMalloc of " + std::to_string(bytes) + " bytes failed");
-  }
+  hipError_t e = dev_alloc(h->dalloc_fn, p, bytes);
+  if (e == hipErrorInvalidValue)
+    return fail(h, PF_E_INVALID, "the installed allocator returned a pointer not aligned to 256 bytes");
+  if (e != hipSuccess)
+    return fail(h, PF_E_OOM, "device allocation of " + std::to_string(bytes) + " bytes failed");
   h->allocs.push_back(*p);
   h->bytes += bytes;
   return PF_OK;
@@ -623,6 +638,101 @@ pf_status do_step(pf_handle* h, const double* y_host, const void* y_dev) {
   }
 }
 
+// Stage plan of the butterfly path (radix < N) into out[0 .. *n_out): mixed
+// radix, tile shape, LDS. The island filter's within-island launch is one
+// stage of radix M and stride 1 (island = true, radix = M). No heap memory,
+// so a caller that must not allocate can plan with it. On failure `err` (errlen
+// bytes) receives the reason.
+pf_status plan_butterfly(uint64_t N, uint64_t radix, int D, int d, size_t tsz, bool island, StagePlan* out,
+                         uint32_t max_out, uint32_t* n_out, char* err, size_t errlen) {
+  const uint32_t n = ilog2(N);
+  const uint32_t b = ilog2(radix);
+  const uint32_t S = (n + b - 1) / b;
+  const uint32_t last = n - (S - 1) * b;
+  const uint32_t nst = island ? 1u : S;
+  if (nst > max_out) {
+    std::snprintf(err, errlen, "%u stages exceed the limit of %u", nst, max_out);
+    return PF_E_UNSUPPORTED;
+  }
+  uint64_t R = 1;
+  for (uint32_t k = 0; k < nst; ++k) {
+    StagePlan sp{};
+    sp.log2r = (k + 1 < S) ? b : last;
+    sp.r = 1u << sp.log2r;
+    sp.R = R;
+    sp.log2R = ilog2(R);
+    R *= sp.r;
+    uint32_t E;
+    if (sp.r <= 64) {
+      sp.blockpath = 0;
+      sp.nt = 256;
+      sp.ppt = ppt_wave(D);
+      E = 2u * sp.nt * sp.ppt;
+      if (E > N) {
+        sp.nt = 64;
+        sp.ppt = 1;
+        E = 128;
+      }
+    } else {
+      sp.blockpath = 1;
+      // 256-thread tiles of at least two groups; larger tiles give longer
+      // contiguous rows at wide strides
+      const uint32_t pb = (uint32_t)ppt_block(D);
+      if (D <= 2 && sp.r <= 256 && N >= 2048u) {
+        sp.nt = 256;
+        sp.ppt = 4;
+      } else if (512u * pb >= 2u * sp.r && 512u * pb <= N) {
+        sp.nt = 256;
+        sp.ppt = (int)pb;
+      } else if (island && sp.log2R == 0 && sp.r <= 1024 && 512u * pb >= sp.r && 512u * pb <= N) {
+        // the within-island launch: one island per 256-thread tile
+        sp.nt = 256;
+        sp.ppt = (int)pb;
+      } else if (sp.r <= 1024 && N >= 2048) {
+        sp.nt = 1024;
+        sp.ppt = 1;
+      } else if (sp.r <= 256) {
+        sp.nt = 256;
+        sp.ppt = 1;
+      } else if (sp.r == 2048 && D <= 4) {
+        sp.nt = 1024;
+        sp.ppt = 2;
+      } else if (sp.r == 4096 && D <= 4) {
+        sp.nt = 1024;
+        sp.ppt = 4;
+      } else if (sp.log2R == 0 && sp.r == 2048 && sp.r <= N) {
+        // stride 1: a group is a contiguous run, so a tile of one group still
+        // loads coalesced rows
+        sp.nt = 1024;
+        sp.ppt = 1;
+      } else {
+        std::snprintf(err, errlen, "stage radix %u is not supported for d = %d (use r <= 1024, or r >= N)",
+                      sp.r, d);
+        return PF_E_UNSUPPORTED;
+      }
+      E = 2u * sp.nt * sp.ppt;
+    }
+    if (E > N || E < (sp.log2R == 0 ? sp.r : 2u * sp.r)) {
+      std::snprintf(err, errlen, "N = %llu is too small for a tile of radix %u", (unsigned long long)N, sp.r);
+      return PF_E_UNSUPPORTED;
+    }
+    sp.C = E / sp.r;
+    sp.log2C = ilog2(sp.C);
+    sp.ntiles = (uint32_t)(N / E);
+    sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
+    sp.xrow = state_row_pitch(sp.C, sp.log2R, sp.log2C);
+    // the within-island launch of the island filter stages no states
+    sp.lds = tile_lds_bytes(island ? 0 : d, D, tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0, sp.xrow);
+    if (sp.lds > 160 * 1024) {
+      std::snprintf(err, errlen, "tile of radix %u needs %zu bytes of LDS (> 160 KiB)", sp.r, sp.lds);
+      return PF_E_UNSUPPORTED;
+    }
+    out[k] = sp;
+  }
+  *n_out = nst;
+  return PF_OK;
+}
+
 pf_status plan_stages(pf_handle* h) {
   const uint64_t N = h->N;
   const uint32_t n = ilog2(N);
@@ -649,89 +759,18 @@ pf_status plan_stages(pf_handle* h) {
     h->g_ntiles = (uint32_t)(N / E);
     return PF_OK;
   }
-  const uint32_t b = ilog2(h->radix);
-  const uint32_t S = (n + b - 1) / b;
-  const uint32_t last = n - (S - 1) * b;
-  uint64_t R = 1;
-  for (uint32_t k = 0; k < S; ++k) {
-    if (h->island && k > 0) break;  // the island filter resamples in one stage of radix M, stride 1
-    StagePlan sp{};
-    sp.log2r = (k + 1 < S) ? b : last;
-    sp.r = 1u << sp.log2r;
-    sp.R = R;
-    sp.log2R = ilog2(R);
-    R *= sp.r;
-    uint32_t E;
-    if (sp.r <= 64) {
-      sp.blockpath = 0;
-      sp.nt = 256;
-      sp.ppt = ppt_wave(h->D);
-      E = 2u * sp.nt * sp.ppt;
-      if (E > N) {
-        sp.nt = 64;
-        sp.ppt = 1;
-        E = 128;
-      }
-    } else {
-      sp.blockpath = 1;
-      // 256-thread tiles of at least two groups; larger tiles give longer
-      // contiguous rows at wide strides
-      const uint32_t pb = (uint32_t)ppt_block(h->D);
-      if (h->D <= 2 && sp.r <= 256 && N >= 2048u) {
-        sp.nt = 256;
-        sp.ppt = 4;
-      } else if (512u * pb >= 2u * sp.r && 512u * pb <= N) {
-        sp.nt = 256;
-        sp.ppt = (int)pb;
-      } else if (h->island && sp.log2R == 0 && sp.r <= 1024 && 512u * pb >= sp.r && 512u * pb <= N) {
-        // the within-island launch: one island per 256-thread tile
-        sp.nt = 256;
-        sp.ppt = (int)pb;
-      } else if (sp.r <= 1024 && N >= 2048) {
-        sp.nt = 1024;
-        sp.ppt = 1;
-      } else if (sp.r <= 256) {
-        sp.nt = 256;
-        sp.ppt = 1;
-      } else if (sp.r == 2048 && h->D <= 4) {
-        sp.nt = 1024;
-        sp.ppt = 2;
-      } else if (sp.r == 4096 && h->D <= 4) {
-        sp.nt = 1024;
-        sp.ppt = 4;
-      } else if (sp.log2R == 0 && sp.r == 2048 && sp.r <= N) {
-        // stride 1: a group is a contiguous run, so a tile of one group still
-        // loads coalesced rows
-        sp.nt = 1024;
-        sp.ppt = 1;
-      } else {
-        return fail(h, PF_E_UNSUPPORTED,
-                    "stage radix " + std::to_string(sp.r) + " is not supported for d = " +
-                        std::to_string(h->d) + " (use r <= 1024, or r >= N)");
-      }
-      E = 2u * sp.nt * sp.ppt;
-    }
-    if (E > N || E < (sp.log2R == 0 ? sp.r : 2u * sp.r))
-      return fail(h, PF_E_UNSUPPORTED, "N = " + std::to_string(N) + " is too small for a tile of radix " +
-                                           std::to_string(sp.r));
-    sp.C = E / sp.r;
-    sp.log2C = ilog2(sp.C);
-    sp.ntiles = (uint32_t)(N / E);
-    sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
-    sp.xrow = state_row_pitch(sp.C, sp.log2R, sp.log2C);
-    // the within-island launch of the island filter stages no states
-    sp.lds = tile_lds_bytes(h->island ? 0 : h->d, h->D, h->tsz, sp.r, sp.C, sp.pad, sp.nt,
-                            sp.blockpath != 0, sp.xrow);
-    if (sp.lds > 160 * 1024)
-      return fail(h, PF_E_UNSUPPORTED, "tile of radix " + std::to_string(sp.r) + " needs " +
-                                           std::to_string(sp.lds) + " bytes of LDS (> 160 KiB)");
-    h->stages.push_back(sp);
-  }
+  StagePlan plan[kMaxStages];
+  uint32_t S = 0;
+  char why[160];
+  const pf_status st = plan_butterfly(N, h->radix, h->D, h->d, h->tsz, h->island != 0, plan, kMaxStages, &S, why,
+                                      sizeof(why));
+  if (st != PF_OK) return fail(h, st, why);
+  h->stages.assign(plan, plan + S);
   return PF_OK;
 }
 
 void release(pf_handle* h) {
-  for (void* p : h->allocs) (void)hipFree(p);
+  for (void* p : h->allocs) dev_free(h->dalloc_fn, p);
   h->allocs.clear();
 }
 
@@ -752,6 +791,15 @@ const char* pf_status_string(pf_status s) {
     case PF_E_STATE: return "handle in error state";
   }
   return "unknown status";
+}
+
+pf_status pf_set_allocator(void* (*alloc)(size_t, void*), void (*free_)(void*, void*), void* ctx) {
+  if ((alloc == nullptr) != (free_ == nullptr)) return PF_E_INVALID;
+  std::lock_guard<std::mutex> lk(g_alloc_mu);
+  g_alloc.alloc = alloc;
+  g_alloc.free_ = free_;
+  g_alloc.ctx = alloc ? ctx : nullptr;
+  return PF_OK;
 }
 
 const char* pf_last_error(const pf_handle* h) {
@@ -797,6 +845,7 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   h->hist_cap = cfg->history ? cfg->history : 1;
   h->full_cycle = cfg->full_cycle != 0;
   h->model_hash = model_hash(model);
+  h->dalloc_fn = current_allocator();
   if (cfg->ess_threshold != 0.0) {
     const double th = cfg->ess_threshold;
     std::string why;
@@ -1244,5 +1293,6 @@ pf_status pf_info(pf_handle* h, pf_info_t* out) {
   out->t = (uint32_t)h->t;
   return PF_OK;
 }
+
 
 }  // extern "C"

@@ -224,3 +224,110 @@ def test_batch_create_rejects_invalid_arguments(lib):
     assert b"filter 1" in lib.pf_batch_last_error(None)
     assert lib.pf_batch_destroy(None) == 0
     assert lib.pf_batch_step(None, None, None) == -1
+
+
+class _CountingAllocator:
+    """Hands out fake, 256-byte aligned addresses (nothing is dereferenced on
+    the host) and records every alloc and free."""
+
+    def __init__(self, misalign=False, fail_after=None):
+        self.next = 1 << 40
+        self.live = {}
+        self.allocs = []
+        self.frees = []
+        self.misalign = misalign
+        self.fail_after = fail_after
+
+    def alloc(self, n):
+        if self.fail_after is not None and len(self.allocs) >= self.fail_after:
+            return None
+        p = self.next + (8 if self.misalign else 0)
+        self.next += (n + 4095) & ~4095
+        self.live[p] = n
+        self.allocs.append((p, n))
+        return p
+
+    def free(self, p):
+        assert p in self.live, "free of a pointer the allocator did not hand out"
+        del self.live[p]
+        self.frees.append(p)
+
+
+@pytest.fixture
+def restore_allocator(lib):
+    import paper_1812_01502_amd as P
+    saved = dict(P._allocator)
+    yield P
+    P.set_allocator("hip")
+    P._allocator.clear()
+    P._allocator.update(saved)
+
+
+def test_set_allocator_argument_checks(lib):
+    from paper_1812_01502_amd import _lib as L
+    f = L.FREE_FN(lambda p, c: None)
+    a = L.ALLOC_FN(lambda n, c: None)
+    assert lib.pf_set_allocator(a, L.FREE_FN(), None) == -1       # exactly one NULL
+    assert lib.pf_set_allocator(L.ALLOC_FN(), f, None) == -1
+    assert lib.pf_set_allocator(L.ALLOC_FN(), L.FREE_FN(), None) == 0
+
+
+def _batch_args(n_filters=3):
+    from paper_1812_01502_amd import _lib as L
+    m, keep = _model_lg(2)
+    ms = (L.PfModel * n_filters)(*([m] * n_filters))
+    cs = (L.PfConfig * n_filters)()
+    for i in range(n_filters):
+        cs[i] = _cfg(n=4096, radix=4)
+    return ms, cs, keep
+
+
+def test_batch_buffers_come_from_the_installed_allocator(lib, restore_allocator):
+    """Every device buffer of a batch comes from the installed callbacks, and
+    a create that fails afterwards (here: no GPU, so the first upload fails)
+    hands every one of them back through the free callback."""
+    P = restore_allocator
+    ca = _CountingAllocator()
+    P.set_allocator("custom", alloc=ca.alloc, free=ca.free)
+    ms, cs, keep = _batch_args()
+    h = ctypes.c_void_p()
+    st = lib.pf_batch_create(ms, cs, 3, None, ctypes.byref(h))
+    assert st != 0 and h.value is None
+    assert len(ca.allocs) >= 10                     # the pools and tables of the batch
+    assert sorted(ca.frees) == sorted(p for p, _ in ca.allocs)
+    assert not ca.live
+
+
+def test_handle_buffers_come_from_the_installed_allocator(lib, restore_allocator):
+    P = restore_allocator
+    ca = _CountingAllocator()
+    P.set_allocator("custom", alloc=ca.alloc, free=ca.free)
+    m, keep = _model_lg(2)
+    c = _cfg()
+    h = ctypes.c_void_p()
+    st = lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h))
+    assert st != 0 and h.value is None
+    assert len(ca.allocs) >= 1
+    assert sorted(ca.frees) == sorted(p for p, _ in ca.allocs) and not ca.live
+
+
+def test_allocator_failures_are_reported(lib, restore_allocator):
+    """A NULL from the allocator is PF_E_OOM; a pointer that is not
+    256-byte aligned is PF_E_INVALID and goes back to the allocator."""
+    P = restore_allocator
+    ms, cs, keep = _batch_args()
+    h = ctypes.c_void_p()
+    ca = _CountingAllocator(fail_after=4)
+    P.set_allocator("custom", alloc=ca.alloc, free=ca.free)
+    assert lib.pf_batch_create(ms, cs, 3, None, ctypes.byref(h)) == -3
+    assert len(ca.allocs) == 4 and not ca.live
+    cm = _CountingAllocator(misalign=True)
+    P.set_allocator("custom", alloc=cm.alloc, free=cm.free)
+    assert lib.pf_batch_create(ms, cs, 3, None, ctypes.byref(h)) == -1
+    assert b"aligned" in lib.pf_batch_last_error(None)
+    assert len(cm.allocs) == 1 and not cm.live
+    m, keep2 = _model_lg(2)
+    c = _cfg()
+    assert lib.pf_create(ctypes.byref(m), ctypes.byref(c), None, ctypes.byref(h)) == -1
+    assert b"aligned" in lib.pf_last_error(None)
+    assert not cm.live
