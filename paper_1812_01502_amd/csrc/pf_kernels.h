@@ -940,7 +940,9 @@ __device__ __forceinline__ void draw_run(const T* col, const T* us, int* pos, ui
   for (int k = 0; k < K; ++k) pos[k] = (int)pk[k];
 }
 
-template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
+// ISL: compiled for the within-island launch only (kStepIsland set, no
+// propagation), which keeps the registers of phase C out of the large tiles.
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL, bool ISL = false>
 __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const uint32_t tile,
                                                unsigned char* smem) {
   constexpr int NLOC = 2 * PPT;
@@ -959,7 +961,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   LdsCarve lc;
   const uint32_t xrow = a.xrow;
   const size_t xplane = (size_t)r * xrow;
-  const bool island = (a.flags & kStepIsland) != 0u;
+  const bool island = ISL || (a.flags & kStepIsland) != 0u;
   T* xs = reinterpret_cast<T*>(smem + lc.take(island ? 0 : (size_t)d * xplane * sizeof(T)));
   T* scl = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
   T* scu = reinterpret_cast<T*>(smem + lc.take((size_t)C * P * sizeof(T)));
@@ -975,7 +977,7 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
   const uint64_t N = a.N;
   const T off = (a.flags & kStepLwRaw) != 0u ? (T)0 : (T)read_offset(a.ctl, a.u);
   const bool weight = (a.flags & kStepWeight) != 0u;
-  const bool prop = (a.flags & kStepPropagate) != 0u;
+  const bool prop = !ISL && (a.flags & kStepPropagate) != 0u;
   const bool lwz = (a.flags & kStepLwZero) != 0u;
   T y[D];
 #pragma unroll
@@ -1293,11 +1295,11 @@ __device__ __forceinline__ void step_tile_body(const StepArgs<T, S>& a, const ui
 
 // Single filter: block b processes tile xcd_tile(b); block 0 also does the
 // step's bookkeeping.
-template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL>
+template <int D, int MK, typename T, typename S, int NT, int PPT, bool BLOCKPATH, bool FULL, bool ISL = false>
 __global__ void __launch_bounds__(NT) pf_step_tile(StepArgs<T, S> a) {
   extern __shared__ __align__(16) unsigned char smem[];
   if (blockIdx.x == 0) step_bookkeeping(a);
-  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH, FULL>(a, xcd_tile(blockIdx.x, a.ntiles), smem);
+  step_tile_body<D, MK, T, S, NT, PPT, BLOCKPATH, FULL, ISL>(a, xcd_tile(blockIdx.x, a.ntiles), smem);
 }
 
 // ---------------------------------------------------------------------------

@@ -37,6 +37,7 @@ struct LaunchReq {
   int ppt;       // particle pairs per thread
   int blockpath; // tile kernels: 1 = r > 64
   int full;      // tile kernels: d equals the compiled dimension
+  int island;    // tile kernels: the within-island launch of the island filter
   uint32_t grid;
   size_t lds;    // dynamic LDS bytes
   uint32_t tile_elems;  // global draw: particles per weight tile
@@ -112,7 +113,8 @@ static hipError_t launch_step_tile(const LaunchReq& rq, const StepArgs<T, S>& a,
     return hipGetLastError();
   }
   if (rq.nt == 1024 && rq.ppt == 1) {
-    auto k = pf_step_tile<D, MK, T, S, 1024, 1, true, FULL>;
+    auto k = rq.island ? pf_step_tile<D, MK, T, S, 1024, 1, true, FULL, true>
+                       : pf_step_tile<D, MK, T, S, 1024, 1, true, FULL>;
     hipError_t e = ensure_lds(k, rq.lds);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
@@ -120,14 +122,16 @@ static hipError_t launch_step_tile(const LaunchReq& rq, const StepArgs<T, S>& a,
   }
   if constexpr (D <= 4) {
     if (rq.nt == 1024 && rq.ppt == 2) {
-      auto k = pf_step_tile<D, MK, T, S, 1024, 2, true, FULL>;
+      auto k = rq.island ? pf_step_tile<D, MK, T, S, 1024, 2, true, FULL, true>
+                       : pf_step_tile<D, MK, T, S, 1024, 2, true, FULL>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);
       return hipGetLastError();
     }
     if (rq.nt == 1024 && rq.ppt == 4) {
-      auto k = pf_step_tile<D, MK, T, S, 1024, 4, true, FULL>;
+      auto k = rq.island ? pf_step_tile<D, MK, T, S, 1024, 4, true, FULL, true>
+                       : pf_step_tile<D, MK, T, S, 1024, 4, true, FULL>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
       hipLaunchKernelGGL(k, dim3(rq.grid), dim3(1024), rq.lds, st, a);

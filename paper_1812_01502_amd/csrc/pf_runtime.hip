@@ -275,6 +275,7 @@ pf_status run_island_step(pf_handle* h, const double* y_host, const void* y_dev)
   rq.ppt = sp.ppt;
   rq.blockpath = sp.blockpath;
   rq.full = h->d == h->D ? 1 : 0;
+  rq.island = 1;
   rq.grid = sp.ntiles;
   rq.lds = sp.lds;
   hipError_t e = launch(h, rq, &a);

@@ -55,11 +55,11 @@ def test_torch_allocator_batch():
     import paper_1812_01502_amd as P
     P.set_allocator("torch")
     models = [W.random_stable_lg(d, 40 + d) for d in (1, 4)]
+    y = torch.zeros(sum(m.d for m in models), dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
     base = torch.cuda.memory_allocated()
     b = P.BatchFilter(models, [4096, 8192], [8, 16], [1, 2])
     assert torch.cuda.memory_allocated() > base
-    y = torch.zeros(sum(m.d for m in models), dtype=torch.float32, device="cuda")
     b.step(y.data_ptr())
     recs = b.estimates()
     assert all(r["valid"] for r in recs)
