@@ -1,20 +1,27 @@
 """Benchmark of the butterfly-interaction particle filter on one MI355X.
 
-Workload (default): the 8-D linear-Gaussian model (A = 0.9 I + 0.05 O, Q = I,
-H = I, R = 0.5 I), N = 2^20 particles, radix 64 (stages 64, 64, 64, 4),
-multinomial resampling, FP32 states and log-weights, FP64 log-normaliser;
-synthetic observations simulated from the model (seed 2). One "step" is one
-filter time step over all N particles: log-weight -> group resample ->
-gather -> propagate (+ estimate partials and the final reduction).
+Headline workload: the stochastic volatility model (x' = 0.95 x + 0.25 z,
+y = 0.6 exp(x / 2) e, x_0 from the stationary law), N = 2^24 particles,
+radix 64 (stages 64, 64, 64, 64), multinomial resampling, FP32 states and
+log-weights, FP64 log-normaliser; synthetic observations simulated from the
+model (seed 3). One "step" is one filter time step over all N particles:
+log-weight -> group resample -> gather -> propagate (+ estimate partials and
+the deferred final reduction).
 
-Printed (one JSON line): particle-steps/s of the butterfly path with the
-observations already in device memory, the global-resampling bootstrap
-filter (r = N) on the same input and its speedup, p50/p99 step latency,
-the roofline of the step kernel (algorithmic bytes / measured time against
-the 8 TB/s HBM peak), and the FP64 oracle timed on the host as a baseline.
+Printed (one JSON line): particle-steps/s of the headline with the
+observations already in device memory, its p50/p99 step latency and the
+roofline of the step kernel (algorithmic bytes / measured time against the
+8 TB/s HBM peak); for the same model and N every radix in {32, 64, 256,
+1024} and the global-resampling bootstrap filter (r = N), each with FP32 and
+BF16 state storage, and the speedups over the global filter; the full-cycle,
+island and ESS-gated variants; the 8-D linear-Gaussian model at N = 2^20
+(radices 2, 4, 32, 64 and N); the batched and serving workloads; and the
+FP64 oracle timed on the host as a baseline.
 
-Usage: python bench.py [--steps K] [--warmup W] [--gpus 1] [--radix 64]
-       python bench.py --mode profile   (kernel-only run for rocprofv3)
+Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
+       python bench.py --mode profile [--workload sv|lg8] [--radix R] [--dtype f32|bf16]
+                       [--profile-island | --profile-adaptive | --profile-global]
+                       (one filter's steps only, for rocprofv3)
 """
 from __future__ import annotations
 
@@ -31,8 +38,9 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0
 # rocprofv3 counter summaries of the step kernel, per workload
-PROFILE_SUMMARY = {"lg8": os.path.join(ROOT, "profiles", "pf_step_tile_lg8_n2p20_r64.json"),
-                   "sv": os.path.join(ROOT, "profiles", "pf_step_tile_sv_n2p24_r64.json")}
+PROFILE_SUMMARY = {("lg8", 64, "f32"): os.path.join(ROOT, "profiles", "pf_step_tile_lg8_n2p20_r64.json"),
+                   ("sv", 64, "f32"): os.path.join(ROOT, "profiles", "pf_step_tile_sv_n2p24_r64.json")}
+STATE_BYTES = {"f32": 4, "bf16": 2, "f64": 8}
 KERNEL_SOURCES = ["paper_1812_01502_amd/csrc/pf_kernels.h", "paper_1812_01502_amd/csrc/pf_device.h"]
 
 
@@ -69,6 +77,8 @@ def timed_run(flt, yd, steps, d):
 
 
 def per_step_latency(flt, yd, steps, d):
+    """p50 / p99 / mean of single-step launches (HIP events around each),
+    continuing the filter with the next observations ``yd[0 .. steps)``."""
     import numpy as np
     import torch
     evs = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
@@ -85,7 +95,8 @@ def per_step_latency(flt, yd, steps, d):
 
 def cpu_baseline(model, N, radix, ys, budget_s=12.0):
     """The FP64 oracle as it stands, single-threaded, on the same workload:
-    as many time steps of N particles as fit in about budget_s seconds."""
+    as many time steps of N particles as fit in about budget_s seconds (at
+    least one)."""
     from threadpoolctl import threadpool_limits
     from oracle import ButterflyOracle
     with threadpool_limits(limits=1):
@@ -155,22 +166,19 @@ def batched_bench(steps: int, warmup: int):
     }
 
 
-def serving_bench(window_s: float = 1.0, rate: float = 2000.0, seed: int = 5):
-    """The serving workload: Poisson arrivals (``rate`` streams/s over
-    ``window_s``) of SV or 4-D LG streams (half each), N uniform over
-    {2^12, 2^16, 2^20}, 50..500 observations each, one observation per
-    millisecond; slot pools sized from the expected concurrency within an
-    HBM budget; continuous batching on one GPU."""
-    import math
+def serving_requests(rate: float, window_s: float, seed: int = 5):
+    """Poisson arrivals (``rate`` streams/s over ``window_s``) of SV or 4-D LG
+    streams (half each), N uniform over {2^12, 2^16, 2^20}, 50..500
+    observations each, one observation per millisecond; observations are
+    windows of one long simulated path per model."""
     import numpy as np
     import workloads as W
-    from paper_1812_01502_amd.serving import Server, StreamRequest, slot_footprint
+    from paper_1812_01502_amd.serving import StreamRequest
     rng = np.random.Generator(np.random.PCG64(seed))
     models = {"sv": W.sv_model(), "lg4": W.random_stable_lg(4, 5004)}
     Ns = [1 << 12, 1 << 16, 1 << 20]
-    cadence = 1e-3
+    sim = {name: W.simulate(m, 20000, seed=seed)[1].reshape(20000, -1) for name, m in models.items()}
     t, reqs = 0.0, []
-    sim = {}
     while True:
         t += rng.exponential(1.0 / rate)
         if t > window_s:
@@ -178,26 +186,32 @@ def serving_bench(window_s: float = 1.0, rate: float = 2000.0, seed: int = 5):
         name = "sv" if rng.random() < 0.5 else "lg4"
         N = Ns[int(rng.integers(0, 3))]
         T = int(rng.integers(50, 501))
-        if name not in sim:   # one long simulated path per model; streams take windows of it
-            sim[name] = W.simulate(models[name], 20000, seed=seed)[1].reshape(20000, -1)
         o = int(rng.integers(0, 20000 - T))
         reqs.append(StreamRequest(stream_id=len(reqs), model=name, n_particles=N,
                                   observations=sim[name][o:o + T], arrival_s=t,
-                                  seed=77 + len(reqs), cadence_s=cadence))
-    budget = 24 << 30
-    mean_T = 275.0
-    pools = {}
-    for name in models:
-        for N in Ns:
-            want = math.ceil(1.5 * rate / 6.0 * mean_T * cadence)
-            cap = int((budget / 6) // slot_footprint(models[name].d, N))
-            pools[(name, N)] = max(1, min(want, cap))
-    srv = Server(models, pools, radix=64)
-    _, stats = srv.run(reqs, realtime=True, max_wall_s=300)
-    srv.close()
-    stats.update(workload=f"Poisson {rate:g}/s over {window_s:g} s, SV or LG-4, N in 2^12/2^16/2^20, "
-                          f"50..500 observations at 1 ms", pools={f"{k[0]} N={k[1]}": v for k, v in pools.items()})
-    return stats
+                                  seed=77 + len(reqs), cadence_s=1e-3))
+    return models, reqs
+
+
+def serving_bench(window_s: float = 5.0, rates=(250.0, 500.0, 700.0, 1000.0, 2000.0), seed: int = 5):
+    """The serving workload at several offered loads: continuous batching
+    over re-bindable slots (admission by device footprint against a 24 GiB
+    budget), per-observation latency from the observation's availability to
+    its estimate in host memory. The offered load is the stream mix's
+    particle-steps per second."""
+    import numpy as np
+    from paper_1812_01502_amd.serving import Server
+    points = []
+    for rate in rates:
+        models, reqs = serving_requests(rate, window_s, seed)
+        offered = sum(q.observations.shape[0] * q.n_particles for q in reqs) / window_s
+        srv = Server(models, max_slots=1024, hbm_budget=24 << 30, radix=64, pipeline=3, max_substeps=8)
+        _, st = srv.run(reqs, realtime=True, max_wall_s=240)
+        srv.close()
+        st.update(rate_streams_per_s=rate, offered_particle_steps_per_s=offered)
+        points.append({k: (round(v, 3) if isinstance(v, float) else v) for k, v in st.items()})
+    return {"workload": f"Poisson arrivals over {window_s:g} s, SV or LG-4 (half each), N in 2^12/2^16/2^20, "
+                        f"50..500 observations at 1 ms", "window_s": window_s, "load_points": points}
 
 
 def island_size(args, N: int) -> int:
@@ -225,9 +239,11 @@ def adaptive_bytes(d: int, state_bytes: int, stages: float) -> float:
     return (row + 4) + 2 * row * stages + 2 * row
 
 
-def load_traffic(path, n_launch_bytes):
+def load_traffic(path):
     """HBM traffic per launch from the committed rocprofv3 counter summary,
     if it was taken on the current kernel sources; else None."""
+    if path is None:
+        return None
     try:
         with open(path) as f:
             prof = json.load(f)
@@ -238,29 +254,155 @@ def load_traffic(path, n_launch_bytes):
     return prof.get("hbm_bytes_per_launch")
 
 
+class Legs:
+    """Timed runs of single filters on one workload (model, N, observations
+    in device memory): every leg creates a filter, runs W untimed steps,
+    times K steps with HIP events around one pf_run, and closes it."""
+
+    def __init__(self, name, cfg, N, K, Wm, stream):
+        import torch
+        import workloads as W
+        self.name, self.cfg, self.N, self.K, self.Wm = name, cfg, N, K, Wm
+        self.model = cfg["model"]
+        self.d = self.model.d
+        self.stream = stream
+        # W + 2 K observations: warm-up, timed steps, then the latency steps
+        _, self.ys = W.simulate(self.model, Wm + 2 * K, seed=cfg["seed_obs"])
+        self.yd = torch.tensor(self.ys, dtype=torch.float32, device="cuda").contiguous()
+        self.yd64 = torch.tensor(self.ys, dtype=torch.float64, device="cuda").contiguous()
+
+    def make(self, radix, dtype="f32", **kw):
+        import paper_1812_01502_amd as P
+        return P.Filter(self.model, self.N, radix, dtype=dtype, seed=self.cfg["seed_pf"],
+                        history=kw.pop("history", 4), stream=self.stream.cuda_stream, **kw)
+
+    def y(self, dtype):
+        return self.yd64 if dtype == "f64" else self.yd
+
+    def time(self, flt, dtype="f32"):
+        """(wall seconds, event seconds) of K steps after W warm-up steps."""
+        yd = self.y(dtype)
+        flt.run(yd.data_ptr(), self.Wm, self.d)
+        return timed_run(flt, yd[self.Wm:], self.K, self.d)
+
+    def leg(self, radix, dtype="f32", bytes_per=None, keep=False, **kw):
+        """One timed filter: throughput, time per step, HBM fraction on the
+        algorithmic bytes ``bytes_per`` per particle-step (default: the fused
+        butterfly step, or the global path's for r >= N)."""
+        flt = self.make(radix, dtype, **kw)
+        info = flt.info()
+        wall, ev = self.time(flt, dtype)
+        s = STATE_BYTES[dtype]
+        if bytes_per is None:
+            bytes_per = algorithmic_bytes(self.d, s, "global" if radix >= self.N else "butterfly")
+        out = dict(particle_steps_per_s=self.N * self.K / wall, ms_per_step=wall / self.K * 1e3,
+                   avg_step_us=ev / self.K * 1e6, bytes_per_particle_step=bytes_per,
+                   hbm_frac=bytes_per * self.N / (ev / self.K) / 1e9 / HBM_PEAK_GBS,
+                   stages=info["stages"])
+        if keep:
+            return out, flt
+        flt.close()
+        return out, None
+
+
+def safe(fn, *a, **kw):
+    """Run one bench leg; a failure is recorded in the output instead of
+    ending the run."""
+    try:
+        return fn(*a, **kw)
+    except Exception as e:   # noqa: BLE001 - reported in the JSON line
+        return {"error": f"{type(e).__name__}: {e}"}
+
+
+def variants(L: Legs, radix: int, island_M: int):
+    """Full-cycle, island and ESS-gated filters on one workload."""
+    import numpy as np
+    d, N, K = L.d, L.N, L.K
+    B = algorithmic_bytes(d, 4, "butterfly")
+    out = {}
+
+    def full():
+        fc, _ = L.leg(radix, bytes_per=None, full_cycle=True)
+        S = len(fc["stages"])
+        fc.update(stages_per_step=S, bytes_per_particle_step=S * B, hbm_frac=fc["hbm_frac"] * S)
+        return fc
+    out["full_cycle"] = safe(full)
+
+    def island():
+        Bi = island_bytes(d, 4)
+        r, _ = L.leg(2, bytes_per=Bi, island=island_M)
+        r.update(island_size=island_M, islands=N // island_M, island_stages=(N // island_M).bit_length() - 1,
+                 launches=("within-island tile kernel, island stages (" +
+                           ("blocks of 1024 islands, then one block" if N // island_M > 1024 else "one block") +
+                           "), island gather"))
+        return r
+    out["island"] = safe(island)
+
+    def adaptive():
+        theta = 0.5
+        flt = L.make(radix, history=K, ess_threshold=theta)
+        wall, ev = L.time(flt)
+        stages_run = [int(r["stage"]) for r in flt.history(K)]
+        flt.close()
+        s_mean = float(np.mean(stages_run)) if stages_run else 0.0
+        Ba = adaptive_bytes(d, 4, s_mean)
+        return dict(ess_threshold=theta, radix=radix, stages_per_step_mean=s_mean,
+                    particle_steps_per_s=N * K / wall, ms_per_step=wall / K * 1e3,
+                    bytes_per_particle_step=Ba, hbm_frac=Ba * N / (ev / K) / 1e9 / HBM_PEAK_GBS,
+                    launches_per_step=3 + 2 * len(L.make(radix).info()["stages"]))
+    out["adaptive"] = safe(adaptive)
+    return out
+
+
+def profile_mode(args, L: Legs):
+    """One filter's warm-up and timed steps (for rocprofv3), then a plain copy
+    of known size (counter calibration)."""
+    import torch
+    if args.profile_island:
+        flt = L.make(2, args.dtype, island=island_size(args, L.N))
+    elif args.profile_adaptive:
+        flt = L.make(args.radix, args.dtype, ess_threshold=0.5)
+    elif args.profile_global:
+        flt = L.make(L.N, args.dtype)
+    else:
+        flt = L.make(args.radix, args.dtype)
+    wall, ev_s = L.time(flt, args.dtype)
+    flt.close()
+    src = torch.empty(1 << 27, dtype=torch.float32, device="cuda")   # 512 MiB
+    src.fill_(1.0)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"profile_run": True, "copy_bytes": src.numel() * 4, "warmup": L.Wm, "steps": L.K,
+                      "avg_step_us": ev_s / L.K * 1e6}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=500)
-    ap.add_argument("--warmup", type=int, default=500,
-                    help="untimed steps first: the step time settles after a few hundred launches")
-    ap.add_argument("--radix", type=int, default=64)
-    ap.add_argument("--n", type=int, default=1 << 20)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=100,
+                    help="untimed steps of every filter before its timed steps")
+    ap.add_argument("--radix", type=int, default=64, help="radix of the headline (and of --mode profile)")
+    ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32", help="--mode profile: state storage")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--extra-radices", default="2,4,32")
-    ap.add_argument("--workload", choices=["lg8", "sv"], default="lg8",
-                    help="lg8: 8-D LG, N = 2^20 (default); sv: stochastic volatility, N = 2^24")
+    ap.add_argument("--workload", choices=["sv", "lg8"], default="sv",
+                    help="--mode profile: sv (stochastic volatility, N = 2^24) or lg8 (8-D LG, N = 2^20)")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-filters section")
     ap.add_argument("--batch-only", action="store_true", help="print only the batched-filters section")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving section")
     ap.add_argument("--serve-only", action="store_true", help="print only the serving section")
-    ap.add_argument("--island", type=int, default=0, help="island size of the island-filter section")
+    ap.add_argument("--no-lg8", action="store_true", help="skip the 8-D LG section")
+    ap.add_argument("--island", type=int, default=0, help="island size of the island-filter sections")
     ap.add_argument("--profile-island", action="store_true",
                     help="--mode profile: run the island filter instead of the butterfly filter")
     ap.add_argument("--profile-adaptive", action="store_true",
                     help="--mode profile: run the ESS-gated filter (theta 0.5) instead")
-    ap.add_argument("--serve-window", type=float, default=1.0, help="arrival window of the serving run (s)")
+    ap.add_argument("--profile-global", action="store_true",
+                    help="--mode profile: run the global bootstrap filter (r = N) instead")
+    ap.add_argument("--serve-window", type=float, default=5.0, help="arrival window of each serving load point (s)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py runs on one GPU only: this build has no multi-GPU path "
@@ -280,140 +422,75 @@ def main():
     if args.serve_only:
         print(json.dumps({"serving": serving_bench(args.serve_window)}), flush=True)
         return
-    cfg = W.config("c2" if args.workload == "lg8" else "c3")
-    if args.workload == "sv" and args.n == 1 << 20:
-        args.n = cfg["N"]
-    model, N, d = cfg["model"], args.n, cfg["model"].d
     K, Wm = args.steps, args.warmup
-    _, ys = W.simulate(model, Wm + K, seed=cfg["seed_obs"])
-    yd = torch.tensor(ys, dtype=torch.float32, device="cuda").contiguous()
     stream = torch.cuda.current_stream()
-
-    def make(radix, full_cycle=False):
-        return P.Filter(model, N, radix, seed=cfg["seed_pf"], history=4,
-                        stream=stream.cuda_stream, full_cycle=full_cycle)
-
-    def make_island(M):
-        return P.Filter(model, N, 2, seed=cfg["seed_pf"], history=4, stream=stream.cuda_stream, island=M)
-
     if args.mode == "profile":
-        # step kernels only (for rocprofv3), then a plain copy of known size
-        if args.profile_island:
-            flt = make_island(island_size(args, N))
-        elif args.profile_adaptive:
-            flt = P.Filter(model, N, args.radix, seed=cfg["seed_pf"], history=4, stream=stream.cuda_stream,
-                           ess_threshold=0.5)
-        else:
-            flt = make(args.radix)
-        flt.run(yd.data_ptr(), Wm, d)
-        wall, ev_s = timed_run(flt, yd[Wm:], K, d)
-        flt.close()
-        src = torch.empty(1 << 27, dtype=torch.float32, device="cuda")   # 512 MiB
-        src.fill_(1.0)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"profile_run": True, "copy_bytes": src.numel() * 4, "warmup": Wm, "steps": K,
-                          "avg_launch_us": ev_s / K * 1e6}))
+        cfg = W.config("c3" if args.workload == "sv" else "c2")
+        profile_mode(args, Legs(args.workload, cfg, cfg["N"], K, Wm, stream))
         return
 
-    # -- butterfly, headline radix ------------------------------------------
-    flt = make(args.radix)
-    plan = flt.info()["stages"]
-    flt.run(yd.data_ptr(), Wm, d)                     # warm-up steps
-    wall, ev_s = timed_run(flt, yd[Wm:], K, d)
-    value = N * K / wall
-    ms_step = wall / K * 1e3
-    p50, p99, mean_us = per_step_latency(flt, yd, min(K, Wm + K), d)
+    # -- 8-D LG, N = 2^20 (run first: the GPU's clocks settle meanwhile) ------
+    lg8 = None
+    if not args.no_lg8:
+        c2 = W.config("c2")
+        L2 = Legs("lg8", c2, c2["N"], K, Wm, stream)
+        lg8 = {"workload": "8-D LG (A = 0.9 I + 0.05 O, Q = I, H = I, R = 0.5 I), N = 2^20, FP32",
+               "per_radix": {}}
+        for r in (2, 4, 32, 64):
+            lg8["per_radix"][str(r)] = safe(lambda r=r: L2.leg(r)[0])
+        g2 = safe(lambda: L2.leg(L2.N)[0])
+        lg8["global_bpf"] = g2
+        if "particle_steps_per_s" in g2:
+            for r, v in lg8["per_radix"].items():
+                if "particle_steps_per_s" in v:
+                    v["speedup_over_global"] = v["particle_steps_per_s"] / g2["particle_steps_per_s"]
+        lg8.update(variants(L2, 64, args.island or 1024))
+        del L2
+
+    # -- stochastic volatility, N = 2^24: every radix, FP32 and BF16 ----------
+    c3 = W.config("c3")
+    L3 = Legs("sv", c3, c3["N"], K, Wm, stream)
+    N, d = L3.N, L3.d
+    sv = {"workload": "stochastic volatility, N = 2^24", "per_radix": {}, "global_bpf": {}}
+    for dt in ("f32", "bf16"):
+        sv["global_bpf"][dt] = safe(lambda dt=dt: L3.leg(N, dt)[0])
+        for r in (32, 256, 1024) + ((64,) if dt == "bf16" else ()):
+            sv["per_radix"][f"{r} {dt}"] = safe(lambda r=r, dt=dt: L3.leg(r, dt)[0])
+    sv.update(variants(L3, 64, args.island or 4096))
+
+    # -- the headline: radix 64, FP32 ------------------------------------------
+    head, flt = L3.leg(args.radix, "f32", keep=True)
+    sv["per_radix"][f"{args.radix} f32"] = head
+    p50, p99, mean_us = per_step_latency(flt, L3.yd[Wm + K:], K, d)
     est = flt.estimate()
     flt.close()
+    for key, v in sv["per_radix"].items():
+        g = sv["global_bpf"].get(key.split()[1], {})
+        if "particle_steps_per_s" in v and "particle_steps_per_s" in g:
+            v["speedup_over_global"] = v["particle_steps_per_s"] / g["particle_steps_per_s"]
     B = algorithmic_bytes(d, 4, "butterfly")
     launch_bytes = B * N
-    avg_launch_s = ev_s / K                            # one step kernel per step
+    avg_launch_s = head["avg_step_us"] * 1e-6     # one step kernel per step
     achieved = launch_bytes / avg_launch_s / 1e9
-    # the counters were taken at the workload's own N only
-    traffic = load_traffic(PROFILE_SUMMARY[args.workload], launch_bytes) if N == cfg["N"] else None
-
-    # -- global bootstrap filter (r = N) ---------------------------------------
-    g = make(N)
-    g.run(yd.data_ptr(), Wm, d)
-    gwall, gev = timed_run(g, yd[Wm:], K, d)
-    gvalue = N * K / gwall
-    gp50, gp99, _ = per_step_latency(g, yd, min(K, Wm + K), d)
-    g.close()
-    Bg = algorithmic_bytes(d, 4, "global")
-
-    # -- other radices --------------------------------------------------------
-    per_radix = {}
-    for r in [int(v) for v in args.extra_radices.split(",") if v]:
-        f2 = make(r)
-        f2.run(yd.data_ptr(), Wm, d)
-        w2, e2 = timed_run(f2, yd[Wm:], K, d)
-        per_radix[str(r)] = dict(particle_steps_per_s=N * K / w2, ms_per_step=w2 / K * 1e3,
-                                 hbm_frac=B * N / (e2 / K) / 1e9 / HBM_PEAK_GBS,
-                                 stages=f2.info()["stages"])
-        f2.close()
-    per_radix[str(args.radix)] = dict(particle_steps_per_s=value, ms_per_step=ms_step,
-                                      hbm_frac=achieved / HBM_PEAK_GBS, stages=plan)
-
-    # -- full augmented resampling per step (all S stages, Algorithm 3) ----------
-    fc = make(args.radix, full_cycle=True)
-    fc.run(yd.data_ptr(), Wm, d)
-    fwall, fev = timed_run(fc, yd[Wm:], K, d)
-    S = len(plan)
-    fc.close()
-    full_cycle = {"stages_per_step": S, "particle_steps_per_s": N * K / fwall, "ms_per_step": fwall / K * 1e3,
-                  "bytes_per_particle_step": S * B,
-                  "hbm_frac_algorithmic": S * B * N / (fev / K) / 1e9 / HBM_PEAK_GBS}
-
-    # -- island filter (AIRPF, Algorithms 4-7) ----------------------------------
-    Mi = island_size(args, N)
-    isl = make_island(Mi)
-    isl.run(yd.data_ptr(), Wm, d)
-    iwall, iev = timed_run(isl, yd[Wm:], K, d)
-    isl.close()
-    Bi = island_bytes(d, 4)
-    island = {"island_size": Mi, "islands": N // Mi, "island_stages": (N // Mi).bit_length() - 1,
-              "particle_steps_per_s": N * K / iwall, "ms_per_step": iwall / K * 1e3,
-              "bytes_per_particle_step": Bi,
-              "hbm_frac_algorithmic": Bi * N / (iev / K) / 1e9 / HBM_PEAK_GBS,
-              "speedup_over_global": (N * K / iwall) / gvalue,
-              "launches": ("within-island tile kernel, island stages (" +
-                           ("blocks of 1024 islands, then one block" if N // Mi > 1024 else "one block") +
-                           "), island gather")}
-
-    # -- ESS-gated stages with a rotating start (Sections 1.2 and 6.4) ----------
-    theta = 0.5
-    ad = P.Filter(model, N, args.radix, seed=cfg["seed_pf"], history=K, stream=stream.cuda_stream,
-                  ess_threshold=theta)
-    ad.run(yd.data_ptr(), Wm, d)
-    awall, aev = timed_run(ad, yd[Wm:], K, d)
-    stages_run = [int(r["stage"]) for r in ad.history(K)]
-    ad.close()
-    s_mean = float(np.mean(stages_run)) if stages_run else 0.0
-    Ba = adaptive_bytes(d, 4, s_mean)
-    adaptive = {"ess_threshold": theta, "radix": args.radix, "stages_per_step_mean": s_mean,
-                "particle_steps_per_s": N * K / awall, "ms_per_step": awall / K * 1e3,
-                "bytes_per_particle_step": Ba,
-                "hbm_frac_algorithmic": Ba * N / (aev / K) / 1e9 / HBM_PEAK_GBS,
-                "launches_per_step": 3 + 2 * len(plan)}
+    traffic = load_traffic(PROFILE_SUMMARY.get(("sv", args.radix, "f32")))
+    gf = sv["global_bpf"].get("f32", {})
 
     out = {
         "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
-        "value": value,
+        "value": head["particle_steps_per_s"],
         "unit": "particle-steps/s",
         "n_gpus": 1,
         "steps": K,
         "warmup": Wm,
-        "ms_per_step": ms_step,
+        "ms_per_step": head["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": f"{args.workload} N=2^{N.bit_length() - 1} radix {args.radix}",
-                   "n_particles": N, "state_dim": d, "radix": args.radix, "stages": plan,
+        "config": {"workload": f"stochastic volatility (x' = 0.95 x + 0.25 z, y = 0.6 e^(x/2) e), "
+                               f"N = 2^{N.bit_length() - 1}, radix {args.radix}, FP32 states",
+                   "n_particles": N, "state_dim": d, "radix": args.radix, "stages": head["stages"],
                    "resampler": "multinomial", "steps_per_run": K, "observations": "device"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS,
@@ -422,23 +499,19 @@ def main():
                      "bytes_per_particle_step": B, "bytes_per_launch": launch_bytes,
                      "avg_launch_us": avg_launch_s * 1e6},
         "latency_us": {"p50": p50, "p99": p99, "mean": mean_us},
-        "global_bpf": {"particle_steps_per_s": gvalue, "ms_per_step": gwall / K * 1e3,
-                       "speedup_butterfly_over_global": value / gvalue,
-                       "bytes_per_particle_step": Bg,
-                       "hbm_frac_algorithmic": Bg * N / (gev / K) / 1e9 / HBM_PEAK_GBS,
-                       "latency_us": {"p50": gp50, "p99": gp99}},
-        "per_radix": per_radix,
-        "full_cycle": full_cycle,
-        "island": island,
-        "adaptive": adaptive,
-        "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"]},
+        "speedup_butterfly_over_global": (head["particle_steps_per_s"] / gf["particle_steps_per_s"]
+                                          if "particle_steps_per_s" in gf else None),
+        "sv": sv,
+        "lg8": lg8,
+        "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"],
+                          "mean": float(est["mean"][0])},
     }
-    if not args.no_batch and args.mode == "bench":
-        out["batched"] = batched_bench(200, 5)
-    if not args.no_serve and args.mode == "bench":
-        out["serving"] = serving_bench(args.serve_window)
+    if not args.no_batch:
+        out["batched"] = safe(batched_bench, 200, 5)
+    if not args.no_serve:
+        out["serving"] = safe(serving_bench, args.serve_window)
     if not args.no_cpu:
-        out["cpu_baseline"] = cpu_baseline(model, N, args.radix, ys)
+        out["cpu_baseline"] = cpu_baseline(L3.model, N, args.radix, L3.ys)
     print(json.dumps(out), flush=True)
 
 

@@ -26,6 +26,15 @@
  *  - Every function returns a pf_status (0 = PF_OK, < 0 = error) and never
  *    aborts or throws. After a device error a handle is poisoned: later
  *    calls return PF_E_STATE until pf_destroy.
+ *  - Numeric failure: the reduction of every step checks its partial sums on
+ *    the device. A step whose weights are not usable (a non-finite sum, e.g.
+ *    from a non-finite device observation or state, or no positive weight)
+ *    gets an estimate record with valid = 0, adds nothing to the
+ *    log-normaliser and sets a sticky per-filter flag on the device: every
+ *    later record is invalid too. Calls that synchronise (pf_estimate,
+ *    pf_history) then return PF_E_NUMERIC (their output is still written),
+ *    and pf_step / pf_run return PF_E_NUMERIC without work until pf_reset,
+ *    pf_set_state or pf_load clears the flag. The handle is not poisoned.
  *  - All pointers marked "host" are ordinary host memory, read or written
  *    before the call returns. Pointers marked "device" are HIP device
  *    memory on the handle's device.
@@ -141,7 +150,9 @@ typedef struct {
                               stages: the number of stages the step ran) */
   uint32_t radix;          /* radix r_k of that stage (full cycle: the radix;
                               island filter: the island size M) */
-  uint32_t valid;          /* 1 if the step has run */
+  uint32_t valid;          /* 1 if the step has run and its weights were
+                              usable; 0 if it has not run, or after a
+                              numeric failure (see Conventions) */
   double log_normaliser;   /* running log p-hat(y_0..y_t), FP64 */
   double ess;              /* (sum w)^2 / (N sum w^2), in [1/N, 1] */
   double max_log_weight;   /* max_i l_i of the step */
@@ -188,7 +199,8 @@ pf_status pf_step(pf_handle* h, const double* y_host);
  * `y_dev + j * y_stride` (device; elements of the compute type: float for
  * F32/BF16 states, double for F64; y_stride >= d). With use_graph != 0 the
  * launches are captured in a HIP graph and replayed once. Asynchronous.
- * Non-finite device observations are not checked. */
+ * A non-finite device observation makes its step a numeric failure (see
+ * Conventions). */
 pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_stride,
                  int32_t use_graph);
 
@@ -253,7 +265,8 @@ pf_status pf_sync(pf_handle* h);
  * per group, with no host data besides two device pointers, so pf_batch_run
  * can capture many steps in one HIP graph.
  * Restrictions: FP32 states, 512 <= N <= 2^30, stage radices <= 64 (no
- * global path), no ancestor recording.
+ * global path), no ancestor recording. A slot may be vacant (n_particles =
+ * 0) and re-bound to another filter at any time (pf_batch_rebind).
  * ------------------------------------------------------------------------ */
 typedef struct pf_batch pf_batch;
 
@@ -297,7 +310,11 @@ pf_status pf_batch_run(pf_batch* b, const float* y_dev, uint32_t n_steps, uint64
                        const uint8_t* active_dev, int32_t use_graph);
 
 /* Estimate record of the last step of every filter (host output, n
- * records; a filter that has not stepped has valid = 0). Synchronises. */
+ * records; a filter that has not stepped has valid = 0, and so has a filter
+ * whose weights became unusable at that step or earlier: a numeric failure
+ * of one filter, e.g. a non-finite observation, leaves the others
+ * unaffected; pf_batch_reset or pf_batch_set_state clears it).
+ * Synchronises. */
 pf_status pf_batch_estimates(pf_batch* b, pf_estimate_t* out);
 
 /* Plan of filter f (radices, tile size, completed steps). */
@@ -320,6 +337,34 @@ pf_status pf_batch_reset(pf_batch* b, uint32_t f, uint64_t seed, uint32_t stream
 
 /* Wait for all work of the batch. */
 pf_status pf_batch_sync(pf_batch* b);
+
+/* Copy the estimate record of every filter (n records, as
+ * pf_batch_estimates) into `out` asynchronously: the copy is enqueued on
+ * the batch's stream after the work enqueued so far, and the call returns
+ * at once. `out` is host memory the caller owns; it must be page-locked
+ * (hipHostMalloc, or a framework's pinned buffer) for the copy to overlap,
+ * and must not be read before the stream (or an event recorded on it after
+ * this call) has completed. Lets a serving loop collect estimates without
+ * stalling the device. */
+pf_status pf_batch_estimates_async(pf_batch* b, pf_estimate_t* out);
+
+/* Re-bind `count` slots of a batch (slots[i], distinct) to other filters
+ * in one call: slot slots[i] takes models[i] and cfgs[i] (host arrays) -
+ * any model, state dimension, N, radix (0: 64, capped at N / 2; no
+ * autotuning), resampler, seed and stream_id that pf_batch_create accepts -
+ * or becomes vacant with cfgs[i].n_particles = 0 (no particle memory, never
+ * steps, records valid = 0; its model is not read). pf_batch_create accepts
+ * vacant slots the same way. The slots' previous device buffers are
+ * released first (a slot bound at create time keeps its share of the
+ * create-time pools until pf_batch_destroy); the new filters are allocated
+ * through the batch's allocator and initialised (Algorithm 1; t = 0). The
+ * packed observation layout follows the slots' current dimensions (vacant
+ * slots take none). Synchronises the batch's stream once. Every other
+ * filter continues exactly as before. Errors: as pf_batch_create for a
+ * slot's configuration (nothing is changed); PF_E_OOM when a filter does
+ * not fit: that slot is left vacant, the others are bound. */
+pf_status pf_batch_rebind(pf_batch* b, uint32_t count, const uint32_t* slots, const pf_model* models,
+                          const pf_config* cfgs);
 
 /* Last error message of the batch ("" if none); NULL: the last failed
  * pf_batch_create of this thread. */

@@ -129,6 +129,14 @@ def _dptr(a):
     return a.ctypes.data_as(L.DPTR)
 
 
+class _VacantModel:
+    """Stand-in model of a vacant batch slot (never read by the library)."""
+    kind, d, phi, sigma, beta = "sv", 1, 0.5, 1.0, 1.0
+
+
+_VACANT_MODEL = _VacantModel()
+
+
 def _pf_model(model, keep: list) -> L.PfModel:
     """``pf_model`` from a model object (arrays kept alive in ``keep``)."""
     m = L.PfModel()
@@ -198,9 +206,10 @@ class Filter:
         self._w_dtype = np.float64 if dtype == "f64" else np.float32
 
     # -- plumbing ----------------------------------------------------------
-    def _check(self, st):
-        if st != L.PF_OK:
+    def _check(self, st, allow_numeric: bool = False):
+        if st != L.PF_OK and not (allow_numeric and st == L.PF_E_NUMERIC):
             raise PfError(st, self._lib.pf_last_error(self._h).decode())
+        return st
 
     @property
     def handle(self):
@@ -247,15 +256,18 @@ class Filter:
                     log_norm=e.log_normaliser, ess=e.ess, max_ell=e.max_log_weight,
                     offset=e.next_offset, mean=np.array(e.mean[:d]), var=np.array(e.var[:d]))
 
-    def estimate(self) -> dict:
+    def estimate(self, check: bool = True) -> dict:
+        """Record of the last step. A numeric failure (the record's ``valid``
+        is 0) raises ``PfError`` unless ``check`` is False."""
         e = L.PfEstimate()
-        self._check(self._lib.pf_estimate(self._h, ctypes.byref(e)))
+        self._check(self._lib.pf_estimate(self._h, ctypes.byref(e)), allow_numeric=not check)
         return self._rec(e, self.d)
 
-    def history(self, n_max: int) -> list:
+    def history(self, n_max: int, check: bool = True) -> list:
+        """The last ``n_max`` records, oldest first (as ``estimate``)."""
         buf = (L.PfEstimate * n_max)()
         n = ctypes.c_uint32()
-        self._check(self._lib.pf_history(self._h, buf, n_max, ctypes.byref(n)))
+        self._check(self._lib.pf_history(self._h, buf, n_max, ctypes.byref(n)), allow_numeric=not check)
         return [self._rec(buf[i], self.d) for i in range(n.value)]
 
     def get_state(self):
@@ -330,23 +342,18 @@ class BatchFilter:
         _default_allocator()
         n = len(models)
         self.n = n
-        self.ds = [int(m.d) for m in models]
+        self.resampler = resampler
+        # n = 0 (model None allowed): a vacant slot
+        self.ds = [int(m.d) if int(N) > 0 else 0 for m, N in zip(models, ns)]
         self.ns = [int(v) for v in ns]
-        self.y_offsets = np.concatenate([[0], np.cumsum(self.ds)[:-1]]).astype(np.int64)
-        self.y_len = int(sum(self.ds))
+        self._layout()
         keep = []
         M = (L.PfModel * n)()
         C = (L.PfConfig * n)()
         sids = stream_ids if stream_ids is not None else range(n)
         for i, (m, N, r, sd, sid) in enumerate(zip(models, ns, radices, seeds, sids)):
-            M[i] = _pf_model(m, keep)
-            C[i].n_particles = int(N)
-            C[i].radix = int(r)
-            C[i].resampler = RESAMPLERS[resampler]
-            C[i].state_dtype = L.PF_DTYPE_F32
-            C[i].seed = int(sd)
-            C[i].stream_id = int(sid)
-            C[i].history = 1
+            M[i] = _pf_model(m if m is not None else _VACANT_MODEL, keep)
+            C[i] = self._config(N, r, sd, sid)
         h = ctypes.c_void_p()
         st = self._lib.pf_batch_create(M, C, n, ctypes.c_void_p(stream) if stream else None,
                                        ctypes.byref(h))
@@ -355,9 +362,65 @@ class BatchFilter:
         self._h = h
         _live.add(self)
 
+    def _config(self, N, r, seed, sid):
+        c = L.PfConfig()
+        c.n_particles = int(N)
+        c.radix = int(r)
+        c.resampler = RESAMPLERS[self.resampler]
+        c.state_dtype = L.PF_DTYPE_F32
+        c.seed = int(seed)
+        c.stream_id = int(sid)
+        c.history = 1
+        return c
+
+    def _layout(self):
+        """Packed observation offsets of the current slot dimensions."""
+        self.y_offsets = np.concatenate([[0], np.cumsum(self.ds)[:-1]]).astype(np.int64)
+        self.y_len = int(sum(self.ds))
+
     def _check(self, st):
         if st != L.PF_OK:
             raise PfError(st, self._lib.pf_batch_last_error(self._h).decode())
+
+    def rebind(self, bindings):
+        """Give slots to other filters in one call (``pf_batch_rebind``):
+        ``bindings`` is a sequence of ``(slot, model, n, radix, seed,
+        stream_id)``; ``n = 0`` leaves the slot vacant. Synchronises, and
+        changes the packed observation layout (``y_offsets``, ``y_len``).
+        Raises ``PfError`` (PF_E_OOM) if a filter did not fit: that slot is
+        then vacant, the others are bound."""
+        bindings = list(bindings)
+        if not bindings:
+            return
+        k = len(bindings)
+        keep = []
+        S = (ctypes.c_uint32 * k)()
+        M = (L.PfModel * k)()
+        C = (L.PfConfig * k)()
+        for i, (f, model, n, radix, seed, sid) in enumerate(bindings):
+            S[i] = int(f)
+            M[i] = _pf_model(model if model is not None and n > 0 else _VACANT_MODEL, keep)
+            C[i] = self._config(n, radix, seed, sid)
+        st = self._lib.pf_batch_rebind(self._h, k, S, M, C)
+        if st not in (L.PF_OK, L.PF_E_OOM):
+            self._check(st)
+        for f, model, n, _, _, _ in bindings:
+            info = self.info(f)
+            self.ns[f] = int(info["n"])
+            self.ds[f] = int(info["d"]) if info["n"] > 0 else 0
+        self._layout()
+        self._check(st)
+
+    def vacate(self, slots):
+        """Release the particle memory of ``slots`` (vacant slots never step)."""
+        self.rebind([(f, None, 0, 0, 0, 0) for f in slots])
+
+    def estimates_async(self, out: np.ndarray):
+        """Enqueue a copy of every record into ``out`` (``ESTIMATE_DTYPE``, n
+        records, page-locked memory) on the batch's stream; read it only
+        after the stream, or an event recorded after this call, completes."""
+        assert out.dtype == ESTIMATE_DTYPE and out.size >= self.n and out.flags.c_contiguous
+        self._check(self._lib.pf_batch_estimates_async(self._h, ctypes.c_void_p(out.ctypes.data)))
 
     def close(self):
         if getattr(self, "_h", None):

@@ -33,7 +33,9 @@ struct FilterHost {
   uint32_t sid, systematic, yoff;
   std::vector<uint32_t> radices;
   uint32_t ntiles, first_block, stage0;
-  size_t x_off, lw_off, part_off;  // element offsets into the pools
+  bool vacant;                     // no filter: no particle memory, never steps
+  float *x, *lw, *part;            // device buffers (in the create-time pools, or own)
+  void* own;                       // the slot's own allocation after a rebind (else null)
 };
 
 struct ClassHost {
@@ -44,6 +46,7 @@ struct ClassHost {
   size_t lds = 0;
   uint32_t* d_block_filter = nullptr;
   uint32_t* d_class_filters = nullptr;
+  size_t cap_blocks = 0, cap_filters = 0;  // capacities of the two maps
 };
 
 }  // namespace
@@ -57,6 +60,7 @@ struct pf_batch {
   // device
   BatchFilter* d_filt = nullptr;
   BatchStage* d_stages = nullptr;
+  size_t cap_stages = 0;
   uint32_t* d_tcur = nullptr;
   ModelParams<float>* d_mp = nullptr;
   float* d_x = nullptr;
@@ -102,6 +106,14 @@ pf_status balloc(pf_batch* b, void** p, size_t bytes) {
   return PF_OK;
 }
 
+// Give back one allocation made by balloc.
+void bfree(pf_batch* b, void* p) {
+  if (!p) return;
+  auto it = std::find(b->allocs.begin(), b->allocs.end(), p);
+  if (it != b->allocs.end()) b->allocs.erase(it);
+  dev_free(b->dalloc_fn, p);
+}
+
 void brelease(pf_batch* b) {
   for (void* p : b->allocs) dev_free(b->dalloc_fn, p);
   b->allocs.clear();
@@ -111,6 +123,11 @@ void brelease(pf_batch* b) {
 // block maps of every class. Host tables only.
 pf_status plan_batch(pf_batch* b) {
   b->stages.clear();
+  b->y_len = 0;
+  for (auto& F : b->fh) {
+    F.yoff = b->y_len;
+    if (!F.vacant) b->y_len += (uint32_t)F.d;
+  }
   for (auto& c : b->classes) {
     const uint32_t E = 2u * kBatchNT * (uint32_t)c.ppt;
     c.nblocks = 0;
@@ -151,12 +168,13 @@ pf_status upload_tables(pf_batch* b) {
   for (uint32_t f = 0; f < b->n; ++f) {
     const FilterHost& F = b->fh[f];
     BatchFilter& T = b->filt[f];
-    T.x[0] = b->d_x + F.x_off;
-    T.x[1] = b->d_x + F.x_off + (size_t)F.d * F.N;
-    T.lw[0] = b->d_lw + F.lw_off;
-    T.lw[1] = b->d_lw + F.lw_off + F.N;
+    if (F.vacant) continue;  // never addressed: no block and no class lists it
+    T.x[0] = F.x;
+    T.x[1] = F.x + (size_t)F.d * F.N;
+    T.lw[0] = F.lw;
+    T.lw[1] = F.lw + F.N;
     T.mp = b->d_mp + f;
-    T.part = b->d_part + F.part_off;
+    T.part = F.part;
     T.ctl = b->d_ctl + f;
     T.rec = b->d_rec + f;
     T.N = F.N;
@@ -173,8 +191,10 @@ pf_status upload_tables(pf_batch* b) {
   }
   hipError_t e = hipMemcpy(b->d_filt, b->filt.data(), sizeof(BatchFilter) * b->n, hipMemcpyHostToDevice);
   if (e != hipSuccess) return bhip(b, e, "filter table upload");
-  e = hipMemcpy(b->d_stages, b->stages.data(), sizeof(BatchStage) * b->stages.size(), hipMemcpyHostToDevice);
-  if (e != hipSuccess) return bhip(b, e, "stage table upload");
+  if (!b->stages.empty()) {
+    e = hipMemcpy(b->d_stages, b->stages.data(), sizeof(BatchStage) * b->stages.size(), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bhip(b, e, "stage table upload");
+  }
   for (auto& c : b->classes) {
     std::vector<uint32_t> map(c.nblocks);
     for (uint32_t f : c.filters)
@@ -193,8 +213,8 @@ pf_status init_filter(pf_batch* b, uint32_t f) {
   const FilterHost& F = b->fh[f];
   StepArgs<float, float> a;
   std::memset(&a, 0, sizeof(a));
-  a.x_out = b->d_x + F.x_off;
-  a.lw_out = b->d_lw + F.lw_off;
+  a.x_out = F.x;
+  a.lw_out = F.lw;
   a.mp = b->d_mp + f;
   a.ctl = b->d_ctl + f;
   a.d = (uint32_t)F.d;
@@ -216,6 +236,7 @@ pf_status init_filter(pf_batch* b, uint32_t f) {
 
 pf_status init_all(pf_batch* b) {
   for (uint32_t f = 0; f < b->n; ++f) {
+    if (b->fh[f].vacant) continue;
     pf_status s = init_filter(b, f);
     if (s != PF_OK) return s;
   }
@@ -236,12 +257,14 @@ pf_status batch_step(pf_batch* b, const float* y_dev, const uint8_t* active) {
   a.y = y_dev;
   a.tcur = b->d_tcur;
   for (auto& c : b->classes) {
+    if (c.filters.empty()) continue;
     a.block_filter = c.d_block_filter;
     BatchReq rq{0, c.D, c.mk, c.ppt, c.full, c.nblocks, c.lds};
     hipError_t e = launch_batch(rq, a, b->stream);
     if (e != hipSuccess) return bhip(b, e, "batched step launch");
   }
   for (auto& c : b->classes) {
+    if (c.filters.empty()) continue;
     a.class_filters = c.d_class_filters;
     BatchReq rq{1, c.D, c.mk, c.ppt, c.full, (uint32_t)c.filters.size(), 0};
     hipError_t e = launch_batch(rq, a, b->stream);
@@ -348,6 +371,134 @@ pf_status autotune(pf_batch* b) {
   return PF_OK;
 }
 
+// Validation of one slot's model and configuration (create and rebind).
+// n_particles = 0 asks for a vacant slot: the model is then not used.
+pf_status check_slot_config(const pf_model* m, const pf_config* c, std::string& msg) {
+  if (!m || !c) {
+    msg = "model or configuration is NULL";
+    return PF_E_INVALID;
+  }
+  if (c->n_particles == 0) return PF_OK;
+  if (validate_model(m, msg) != PF_OK) return PF_E_INVALID;
+  auto bad = [&](pf_status st, const char* why) {
+    msg = why;
+    return st;
+  };
+  if (!is_pow2(c->n_particles) || c->n_particles < 512 || c->n_particles > (1ull << 30))
+    return bad(PF_E_INVALID, "n_particles must be 0 (vacant) or a power of two in [512, 2^30]");
+  if (c->radix != 0 && (!is_pow2(c->radix) || c->radix < 2 || c->radix > 64))
+    return bad(PF_E_INVALID, "radix must be 0 (autotune) or a power of two in [2, 64]");
+  if (c->radix >= c->n_particles) return bad(PF_E_UNSUPPORTED, "the global path (r >= N) is not batched");
+  if (c->resampler != PF_RESAMPLE_MULTINOMIAL && c->resampler != PF_RESAMPLE_SYSTEMATIC)
+    return bad(PF_E_INVALID, "unknown resampler");
+  if (c->state_dtype != PF_DTYPE_F32) return bad(PF_E_UNSUPPORTED, "batched filters use FP32 states");
+  if (c->keep_ancestors) return bad(PF_E_UNSUPPORTED, "keep_ancestors is not batched");
+  if (c->full_cycle) return bad(PF_E_UNSUPPORTED, "full-cycle steps are not batched");
+  if (c->island) return bad(PF_E_UNSUPPORTED, "the island filter is not batched");
+  if (c->ess_threshold != 0.0) return bad(PF_E_UNSUPPORTED, "ESS-gated stages are not batched");
+  return PF_OK;
+}
+
+// Host description of a slot from a checked model and configuration (the
+// device buffers are set by the caller).
+void bind_host(FilterHost& F, const pf_model* m, const pf_config* c, ModelParams<float>* mp) {
+  F = FilterHost{};
+  F.vacant = c->n_particles == 0;
+  if (F.vacant) {
+    F.d = 0;
+    F.D = 1;
+    F.N = 0;
+    return;
+  }
+  F.kind = m->kind;
+  F.d = m->d;
+  F.D = compiled_dim(m->d);
+  fill_params<float>(m, m->d, mp, &F.mk);
+  F.N = c->n_particles;
+  F.autotune = c->radix == 0;
+  F.radix = c->radix == 0 ? std::min<uint64_t>(64, F.N / 2) : c->radix;
+  F.seed = c->seed;
+  F.sid = c->stream_id;
+  F.systematic = c->resampler == PF_RESAMPLE_SYSTEMATIC ? 1u : 0u;
+}
+
+// Classes (one per state dimension and model kind) of the occupied slots. A
+// class that exists keeps its tile (and device maps) while every member
+// still fits it; a new class takes two pairs per thread where every member
+// has at least 1024 particles.
+void rebuild_classes(pf_batch* b) {
+  std::vector<ClassHost> old;
+  old.swap(b->classes);
+  std::map<std::pair<int, int>, size_t> cls_of;
+  for (uint32_t f = 0; f < b->n; ++f) {
+    const FilterHost& F = b->fh[f];
+    if (F.vacant) continue;
+    const auto key = std::make_pair(F.D, F.mk);
+    if (!cls_of.count(key)) {
+      cls_of[key] = b->classes.size();
+      ClassHost ch;
+      ch.D = F.D;
+      ch.mk = F.mk;
+      ch.ppt = 0;
+      for (auto& o : old)
+        if (o.D == F.D && o.mk == F.mk) {
+          ch = o;
+          ch.filters.clear();
+          ch.full = 1;
+          o.d_block_filter = nullptr;
+          o.d_class_filters = nullptr;
+        }
+      b->classes.push_back(ch);
+    }
+    ClassHost& c = b->classes[cls_of[key]];
+    c.filters.push_back(f);
+    if (F.d != F.D) c.full = 0;
+  }
+  for (auto& o : old) {  // classes that lost every member
+    bfree(b, o.d_block_filter);
+    bfree(b, o.d_class_filters);
+  }
+  for (auto& c : b->classes) {
+    uint64_t nmin = ~0ull;
+    for (uint32_t f : c.filters) nmin = std::min(nmin, b->fh[f].N);
+    if (c.ppt == 0) c.ppt = (batch_ppt_ok(c.D, 2) && nmin >= 1024) ? 2 : 1;
+    if (512ull * (uint64_t)c.ppt > nmin) c.ppt = 1;
+  }
+}
+
+// Device tables large enough for the current slots: the stage table and
+// every class's block and member maps (grown, never shrunk).
+pf_status ensure_tables(pf_batch* b) {
+  size_t need = 1;
+  for (auto& F : b->fh)
+    if (!F.vacant) need += ilog2(F.N);  // radix 2 is the longest plan
+  pf_status s;
+  void* p = nullptr;
+  if (need > b->cap_stages) {
+    if ((s = balloc(b, &p, sizeof(BatchStage) * need)) != PF_OK) return s;
+    bfree(b, b->d_stages);
+    b->d_stages = reinterpret_cast<BatchStage*>(p);
+    b->cap_stages = need;
+  }
+  for (auto& c : b->classes) {
+    size_t blocks = 0;
+    for (uint32_t f : c.filters) blocks += b->fh[f].N / 512;
+    if (blocks > c.cap_blocks) {
+      if ((s = balloc(b, &p, sizeof(uint32_t) * blocks)) != PF_OK) return s;
+      bfree(b, c.d_block_filter);
+      c.d_block_filter = reinterpret_cast<uint32_t*>(p);
+      c.cap_blocks = blocks;
+    }
+    if (c.filters.size() > c.cap_filters) {
+      if ((s = balloc(b, &p, sizeof(uint32_t) * c.filters.size())) != PF_OK) return s;
+      bfree(b, c.d_class_filters);
+      c.d_class_filters = reinterpret_cast<uint32_t*>(p);
+      c.cap_filters = c.filters.size();
+    }
+  }
+  return PF_OK;
+}
+
 bool bpoisoned(pf_batch* b) { return b->sticky != PF_OK; }
 
 pf_status bsync(pf_batch* b) {
@@ -379,70 +530,17 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
     return s;
   };
   std::vector<ModelParams<float>> mps(n);
-  std::map<std::pair<int, int>, size_t> cls_of;
-  size_t x_elems = 0, lw_elems = 0;
+  size_t x_elems = 0, lw_elems = 0, part_elems = 0;
   for (uint32_t f = 0; f < n; ++f) {
-    const pf_model* m = models + f;
-    const pf_config* c = cfgs + f;
-    const std::string who = "filter " + std::to_string(f) + ": ";
     std::string msg;
-    if (validate_model(m, msg) != PF_OK) return bail(bfail(b, PF_E_INVALID, who + msg));
-    if (!is_pow2(c->n_particles) || c->n_particles < 512 || c->n_particles > (1ull << 30))
-      return bail(bfail(b, PF_E_INVALID, who + "n_particles must be a power of two in [512, 2^30]"));
-    if (c->radix != 0 && (!is_pow2(c->radix) || c->radix < 2 || c->radix > 64))
-      return bail(bfail(b, PF_E_INVALID, who + "radix must be 0 (autotune) or a power of two in [2, 64]"));
-    if (c->radix >= c->n_particles)
-      return bail(bfail(b, PF_E_UNSUPPORTED, who + "the global path (r >= N) is not batched"));
-    if (c->resampler != PF_RESAMPLE_MULTINOMIAL && c->resampler != PF_RESAMPLE_SYSTEMATIC)
-      return bail(bfail(b, PF_E_INVALID, who + "unknown resampler"));
-    if (c->state_dtype != PF_DTYPE_F32)
-      return bail(bfail(b, PF_E_UNSUPPORTED, who + "batched filters use FP32 states"));
-    if (c->keep_ancestors) return bail(bfail(b, PF_E_UNSUPPORTED, who + "keep_ancestors is not batched"));
-    if (c->full_cycle) return bail(bfail(b, PF_E_UNSUPPORTED, who + "full-cycle steps are not batched"));
-    if (c->island) return bail(bfail(b, PF_E_UNSUPPORTED, who + "the island filter is not batched"));
-    if (c->ess_threshold != 0.0) return bail(bfail(b, PF_E_UNSUPPORTED, who + "ESS-gated stages are not batched"));
+    const pf_status cs = check_slot_config(models + f, cfgs + f, msg);
+    if (cs != PF_OK) return bail(bfail(b, cs, "filter " + std::to_string(f) + ": " + msg));
     FilterHost& F = b->fh[f];
-    F.kind = m->kind;
-    F.d = m->d;
-    F.D = compiled_dim(m->d);
-    fill_params<float>(m, m->d, &mps[f], &F.mk);
-    F.N = c->n_particles;
-    F.autotune = c->radix == 0;
-    F.radix = c->radix;
-    F.seed = c->seed;
-    F.sid = c->stream_id;
-    F.systematic = c->resampler == PF_RESAMPLE_SYSTEMATIC ? 1u : 0u;
-    F.yoff = b->y_len;
-    b->y_len += (uint32_t)m->d;
-    F.x_off = x_elems;
+    bind_host(F, models + f, cfgs + f, &mps[f]);
+    if (F.vacant) continue;
     x_elems += 2ull * F.d * F.N;
-    F.lw_off = lw_elems;
     lw_elems += 2ull * F.N;
-    auto key = std::make_pair(F.D, F.mk);
-    if (!cls_of.count(key)) {
-      cls_of[key] = b->classes.size();
-      ClassHost ch;
-      ch.D = F.D;
-      ch.mk = F.mk;
-      ch.ppt = 1;
-      b->classes.push_back(ch);
-    }
-    b->classes[cls_of[key]].filters.push_back(f);
-    if (F.d != F.D) b->classes[cls_of[key]].full = 0;
-  }
-  // default tile: two pairs per thread where every filter of the class has
-  // at least 1024 particles
-  for (auto& c : b->classes) {
-    uint64_t nmin = ~0ull;
-    for (uint32_t f : c.filters) nmin = std::min(nmin, b->fh[f].N);
-    c.ppt = (batch_ppt_ok(c.D, 2) && nmin >= 1024) ? 2 : 1;
-  }
-  // partial records: at most N / 512 tiles per filter
-  size_t part_elems = 0;
-  for (auto& F : b->fh) {
-    F.part_off = part_elems;
     part_elems += (F.N / 512) * (size_t)partial_stride(F.D);
-    if (F.autotune) F.radix = std::min<uint64_t>(64, F.N / 2);
   }
   pf_status s;
   void* p = nullptr;
@@ -452,6 +550,16 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
   b->d_lw = reinterpret_cast<float*>(p);
   if ((s = balloc(b, &p, sizeof(float) * part_elems)) != PF_OK) return bail(s);
   b->d_part = reinterpret_cast<float*>(p);
+  x_elems = lw_elems = part_elems = 0;
+  for (auto& F : b->fh) {
+    if (F.vacant) continue;
+    F.x = b->d_x + x_elems;
+    F.lw = b->d_lw + lw_elems;
+    F.part = b->d_part + part_elems;
+    x_elems += 2ull * F.d * F.N;
+    lw_elems += 2ull * F.N;
+    part_elems += (F.N / 512) * (size_t)partial_stride(F.D);
+  }
   if ((s = balloc(b, &p, sizeof(Ctl) * n)) != PF_OK) return bail(s);
   b->d_ctl = reinterpret_cast<Ctl*>(p);
   if ((s = balloc(b, &p, sizeof(pf_estimate_t) * n)) != PF_OK) return bail(s);
@@ -462,18 +570,10 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
   b->d_tcur = reinterpret_cast<uint32_t*>(p);
   if ((s = balloc(b, &p, sizeof(BatchFilter) * n)) != PF_OK) return bail(s);
   b->d_filt = reinterpret_cast<BatchFilter*>(p);
-  size_t max_stages = 0;
-  for (auto& F : b->fh) max_stages += ilog2(F.N);  // radix 2 is the longest plan
-  if ((s = balloc(b, &p, sizeof(BatchStage) * max_stages)) != PF_OK) return bail(s);
-  b->d_stages = reinterpret_cast<BatchStage*>(p);
-  for (auto& c : b->classes) {
-    size_t maxblocks = 0;
-    for (uint32_t f : c.filters) maxblocks += b->fh[f].N / 512;
-    if ((s = balloc(b, &p, sizeof(uint32_t) * maxblocks)) != PF_OK) return bail(s);
-    c.d_block_filter = reinterpret_cast<uint32_t*>(p);
-    if ((s = balloc(b, &p, sizeof(uint32_t) * c.filters.size())) != PF_OK) return bail(s);
-    c.d_class_filters = reinterpret_cast<uint32_t*>(p);
-  }
+  rebuild_classes(b);
+  if ((s = ensure_tables(b)) != PF_OK) return bail(s);
+  hipError_t e0 = hipMemset(b->d_rec, 0, sizeof(pf_estimate_t) * n);
+  if (e0 != hipSuccess) return bail(bhip(b, e0, "record clear"));
   hipError_t e = hipMemcpy(b->d_mp, mps.data(), sizeof(ModelParams<float>) * n, hipMemcpyHostToDevice);
   if (e != hipSuccess) return bail(bhip(b, e, "model upload"));
   if ((s = plan_batch(b)) != PF_OK) return bail(s);
@@ -595,11 +695,12 @@ pf_status pf_batch_get_state(pf_batch* b, uint32_t f, float* x_host, float* logw
   pf_status s = bsync(b);
   if (s != PF_OK) return s;
   const FilterHost& F = b->fh[f];
+  if (F.vacant) return bfail(b, PF_E_STATE, "filter " + std::to_string(f) + " is vacant");
   uint32_t t = 0;
   hipError_t e = hipMemcpy(&t, b->d_tcur + f, sizeof(t), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return bhip(b, e, "step counter copy");
-  const float* xs = b->d_x + F.x_off + (t & 1u) * (size_t)F.d * F.N;
-  const float* ws = b->d_lw + F.lw_off + (t & 1u) * (size_t)F.N;
+  const float* xs = F.x + (t & 1u) * (size_t)F.d * F.N;
+  const float* ws = F.lw + (t & 1u) * (size_t)F.N;
   if (x_host) {
     e = hipMemcpy(x_host, xs, sizeof(float) * F.d * F.N, hipMemcpyDeviceToHost);
     if (e != hipSuccess) return bhip(b, e, "state copy");
@@ -628,8 +729,9 @@ pf_status pf_batch_set_state(pf_batch* b, uint32_t f, const float* x_host, const
   pf_status s = bsync(b);
   if (s != PF_OK) return s;
   const FilterHost& F = b->fh[f];
-  float* xs = b->d_x + F.x_off + (t & 1u) * (size_t)F.d * F.N;
-  float* ws = b->d_lw + F.lw_off + (t & 1u) * (size_t)F.N;
+  if (F.vacant) return bfail(b, PF_E_STATE, "filter " + std::to_string(f) + " is vacant");
+  float* xs = F.x + (t & 1u) * (size_t)F.d * F.N;
+  float* ws = F.lw + (t & 1u) * (size_t)F.N;
   hipError_t e = hipMemcpy(xs, x_host, sizeof(float) * F.d * F.N, hipMemcpyHostToDevice);
   if (e != hipSuccess) return bhip(b, e, "state upload");
   if (logw_host) e = hipMemcpy(ws, logw_host, sizeof(float) * F.N, hipMemcpyHostToDevice);
@@ -640,6 +742,7 @@ pf_status pf_batch_set_state(pf_batch* b, uint32_t f, const float* x_host, const
   if (e != hipSuccess) return bhip(b, e, "control copy");
   c.log_norm = log_norm;
   c.t = t;
+  c.fail_t = kNoFail;
   for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
   c.offs[(t % kOffRing) * kOffSlots * kOffStride] = ord_encode(0.0);
   e = hipMemcpy(b->d_ctl + f, &c, sizeof(c), hipMemcpyHostToDevice);
@@ -653,6 +756,7 @@ pf_status pf_batch_reset(pf_batch* b, uint32_t f, uint64_t seed, uint32_t stream
   if (!b || f >= b->n) return PF_E_INVALID;
   if (bpoisoned(b)) return PF_E_STATE;
   FilterHost& F = b->fh[f];
+  if (F.vacant) return bfail(b, PF_E_STATE, "filter " + std::to_string(f) + " is vacant");
   F.seed = seed;
   F.sid = stream_id;
   BatchFilter& T = b->filt[f];
@@ -668,6 +772,82 @@ pf_status pf_batch_reset(pf_batch* b, uint32_t f, uint64_t seed, uint32_t stream
   e = hipMemsetAsync(b->d_rec + f, 0, sizeof(pf_estimate_t), b->stream);
   if (e != hipSuccess) return bhip(b, e, "record clear");
   return bsync(b);
+}
+
+pf_status pf_batch_estimates_async(pf_batch* b, pf_estimate_t* out) {
+  if (!b || !out) return PF_E_INVALID;
+  if (bpoisoned(b)) return PF_E_STATE;
+  hipError_t e = hipMemcpyAsync(out, b->d_rec, sizeof(pf_estimate_t) * b->n, hipMemcpyDeviceToHost, b->stream);
+  if (e != hipSuccess) return bhip(b, e, "record copy");
+  return PF_OK;
+}
+
+pf_status pf_batch_rebind(pf_batch* b, uint32_t count, const uint32_t* slots, const pf_model* models,
+                          const pf_config* cfgs) {
+  if (!b || (count && (!slots || !models || !cfgs))) return PF_E_INVALID;
+  if (bpoisoned(b)) return PF_E_STATE;
+  std::vector<char> seen(b->n, 0);
+  for (uint32_t i = 0; i < count; ++i) {
+    const uint32_t f = slots[i];
+    if (f >= b->n) return bfail(b, PF_E_INVALID, "slot " + std::to_string(f) + " is out of range");
+    if (seen[f]) return bfail(b, PF_E_INVALID, "slot " + std::to_string(f) + " is listed twice");
+    seen[f] = 1;
+    std::string msg;
+    const pf_status cs = check_slot_config(models + i, cfgs + i, msg);
+    if (cs != PF_OK) return bfail(b, cs, "filter " + std::to_string(f) + ": " + msg);
+  }
+  if (count == 0) return PF_OK;
+  pf_status s = bsync(b);
+  if (s != PF_OK) return s;
+  // release first, so that the new filters can reuse the memory
+  for (uint32_t i = 0; i < count; ++i) {
+    FilterHost& F = b->fh[slots[i]];
+    bfree(b, F.own);
+    F = FilterHost{};
+    F.vacant = true;
+  }
+  pf_status first_err = PF_OK;
+  std::vector<uint32_t> bound;
+  for (uint32_t i = 0; i < count; ++i) {
+    const uint32_t f = slots[i];
+    FilterHost& F = b->fh[f];
+    ModelParams<float> mp{};
+    bind_host(F, models + i, cfgs + i, &mp);
+    F.autotune = false;
+    if (F.vacant) continue;
+    // one allocation: states (2 d N), log-weights (2 N), tile records
+    // ((N / 512) (4 + 3 D)), each part 256-byte aligned
+    auto up = [](size_t v) { return (v + 63u) & ~(size_t)63u; };
+    const size_t nx = up(2ull * F.d * F.N), nl = up(2ull * F.N), np = up((F.N / 512) * (size_t)partial_stride(F.D));
+    void* p = nullptr;
+    if ((s = balloc(b, &p, sizeof(float) * (nx + nl + np))) != PF_OK) {
+      F = FilterHost{};
+      F.vacant = true;  // this slot stays vacant; the others are bound
+      if (first_err == PF_OK) first_err = s;
+      continue;
+    }
+    F.own = p;
+    F.x = reinterpret_cast<float*>(p);
+    F.lw = F.x + nx;
+    F.part = F.lw + nl;
+    hipError_t e = hipMemcpy(b->d_mp + f, &mp, sizeof(mp), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return bhip(b, e, "model upload");
+    bound.push_back(f);
+  }
+  rebuild_classes(b);
+  if ((s = ensure_tables(b)) != PF_OK) return s;
+  if ((s = plan_batch(b)) != PF_OK) return s;
+  if ((s = upload_tables(b)) != PF_OK) return s;
+  for (uint32_t f : bound)
+    if ((s = init_filter(b, f)) != PF_OK) return s;
+  for (uint32_t i = 0; i < count; ++i) {
+    const uint32_t f = slots[i];
+    hipError_t e = hipMemsetAsync(b->d_tcur + f, 0, sizeof(uint32_t), b->stream);
+    if (e == hipSuccess) e = hipMemsetAsync(b->d_rec + f, 0, sizeof(pf_estimate_t), b->stream);
+    if (e != hipSuccess) return bhip(b, e, "slot clear");
+  }
+  if ((s = bsync(b)) != PF_OK) return s;
+  return first_err;
 }
 
 const char* pf_batch_last_error(const pf_batch* b) {

@@ -354,13 +354,18 @@ constexpr int kOffEntries = kOffRing * kOffSlots * kOffStride;
 // Steps whose reductions may be deferred and done together.
 constexpr int kMaxPending = 64;
 
+constexpr uint32_t kNoFail = 0xFFFFFFFFu;
 struct Ctl {
   double log_norm;           // running log-normaliser (FP64)
   uint32_t t;                // steps reduced so far (diagnostic)
   // ESS-gated stages: the next stage slot runs (ad_active), the stage it
   // runs, stages run so far in the step, the stage the next step starts at
   uint32_t ad_active, ad_stage, ad_run, ad_next;
-  uint32_t pad[9];
+  // the first step whose weights were unusable (a non-finite partial sum,
+  // or no positive weight), kNoFail if none: that step and every later one
+  // are invalid; reset by the initialisation and by state uploads
+  uint32_t fail_t;
+  uint32_t pad[8];
   long long offs[kOffEntries];  // encoded maxima, [ring][slot * stride]
   double step_off[kMaxPending]; // offset step t subtracted, at t mod kMaxPending
   double dlog[kMaxPending];     // log-normaliser increments of deferred reductions

@@ -208,6 +208,26 @@ inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) 
   };
   const uint32_t skip = r > 64 ? r >> 6 : 0u;
   auto lix = [&](uint32_t q) { return r > 64 ? q + (q >> 6) : q; };
+  // LDS cycles of one access of n <= 64 lanes: per group of lanes served
+  // together, the largest number of distinct addresses that share a bank
+  // (fixed-size arrays: the planner allocates no memory)
+  auto degree = [](const uint32_t* addr, int n, int banks, int lanes_per_cycle) {
+    double tot = 0;
+    for (int g = 0; g < n; g += lanes_per_cycle) {
+      int cnt[64] = {0};
+      int mx = 0;
+      const int e = g + lanes_per_cycle < n ? g + lanes_per_cycle : n;
+      for (int i = g; i < e; ++i) {
+        bool seen = false;
+        for (int j = g; j < i; ++j) seen |= (addr[j] == addr[i]);
+        if (seen) continue;
+        const int bk = (int)(addr[i] % (uint32_t)banks);
+        mx = std::max(mx, ++cnt[bk]);
+      }
+      tot += mx;
+    }
+    return tot;
+  };
   uint32_t best = 0;
   double best_cost = 1e30;
   const uint32_t cands[] = {0, 1, 2, 3, 4, 5, 8};
@@ -215,41 +235,19 @@ inline uint32_t choose_pad_eval(uint32_t r, uint32_t C, uint32_t log2R, int nt) 
     const uint32_t P = r + skip + pad;
     double cost = 0;
     for (int banks : {32, 64}) {
-      auto degree = [&](const std::vector<uint32_t>& addr, int lanes_per_cycle) {
-        double tot = 0;
-        for (size_t g = 0; g < addr.size(); g += lanes_per_cycle) {
-          std::vector<std::vector<uint32_t>> b(banks);
-          int mx = 0;
-          for (size_t i = g; i < g + lanes_per_cycle && i < addr.size(); ++i) {
-            auto& v = b[addr[i] % banks];
-            bool seen = false;
-            for (uint32_t a : v) seen |= (a == addr[i]);
-            if (!seen) v.push_back(addr[i]);
-            mx = std::max<int>(mx, (int)v.size());
-          }
-          tot += mx;
-        }
-        return tot;
-      };
       const int lpc = banks == 32 ? 32 : 64;
+      uint32_t addr[64];
       for (int e = 0; e < 2; ++e) {
-        std::vector<uint32_t> addr;
+        int n = 0;
         for (int l = 0; l < 64 && l < nt; ++l) {
           uint32_t q, c;
           coords(2u * l + e, q, c);
-          addr.push_back(c * P + lix(q));
+          addr[n++] = c * P + lix(q);
         }
-        cost += degree(addr, lpc);
+        cost += degree(addr, n, banks, lpc);
       }
-      if (r <= 64) {
-        std::vector<uint32_t> addr;
-        for (uint32_t l = 0; l < 64; ++l) addr.push_back((l >> log2r) * P + (l & (r - 1)));
-        cost += 2 * degree(addr, lpc);
-      } else {
-        std::vector<uint32_t> addr;
-        for (uint32_t l = 0; l < 64; ++l) addr.push_back(l);
-        cost += 2 * degree(addr, lpc);
-      }
+      for (uint32_t l = 0; l < 64; ++l) addr[l] = r <= 64 ? (l >> log2r) * P + (l & (r - 1)) : l;
+      cost += 2 * degree(addr, 64, banks, lpc);
     }
     cost += 0.01 * pad;  // prefer the smaller pad on ties
     if (cost < best_cost) {

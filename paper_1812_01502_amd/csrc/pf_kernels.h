@@ -180,6 +180,7 @@ __global__ void __launch_bounds__(256) pf_init_kernel(StepArgs<T, S> a) {
       a.ctl->ad_stage = 0u;
       a.ctl->ad_run = 0u;
       a.ctl->ad_next = 0u;
+      a.ctl->fail_t = kNoFail;
     }
   }
 }
@@ -232,9 +233,26 @@ template <int D, typename T> constexpr int fin_batch() {
   return b < 1 ? 1 : (b > 8 ? 8 : b);
 }
 
+// 1 if v is NaN or infinite (minus infinity allowed with neg_inf_ok). The
+// kernels are built assuming no NaN operands, so the test looks at the bits
+// through an opaque register move that the optimiser cannot see through.
+__device__ __forceinline__ uint32_t nonfinite_bits(float v, bool neg_inf_ok) {
+  uint32_t w = __float_as_uint(v);
+  asm volatile("" : "+v"(w));
+  return ((w & 0x7F800000u) == 0x7F800000u && !(neg_inf_ok && w == 0xFF800000u)) ? 1u : 0u;
+}
+__device__ __forceinline__ uint32_t nonfinite_bits(double v, bool neg_inf_ok) {
+  uint64_t w = (uint64_t)__double_as_longlong(v);
+  asm volatile("" : "+v"(w));
+  return ((w & 0x7FF0000000000000ull) == 0x7FF0000000000000ull && !(neg_inf_ok && w == 0xFFF0000000000000ull))
+             ? 1u
+             : 0u;
+}
+
 template <int D, typename T, int NT, int FB>
 __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, uint32_t ntiles,
                                   double* red) {
+  __shared__ uint32_t s_bad[NT / 64];
   constexpr int PS = partial_stride(D);
   constexpr int NR = 4 + 2 * D;  // per wave: [M_w, swin, S, sw2, Mx[D], Mxx[D]]
   constexpr int NW = NT / 64;
@@ -252,6 +270,7 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
     if (lane == 0 && !f.multi) ln0 = f.ctl->log_norm;
   }
   double mt = -INFINITY, swin = 0.0, s = 0.0, sw2 = 0.0, a1[D], a2[D];
+  uint32_t bad = 0u;
 #pragma unroll
   for (int j = 0; j < D; ++j) a1[j] = a2[j] = 0.0;
   for (uint32_t b0 = tid; b0 < ntiles; b0 += NT * FB) {
@@ -263,6 +282,16 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
 #pragma unroll
       for (int v = 0; v < PS; ++v) rec[q][v] = pr[v];
     }
+    // a tile max may be -inf (no positive weight in the tile); every other
+    // value must be finite
+#pragma unroll
+    for (int q = 0; q < FB; ++q)
+      if (b0 + (uint32_t)q * NT < ntiles) {
+        bad |= nonfinite_bits(rec[q][0], true);
+#pragma unroll
+        for (int v = 1; v < 4 + 2 * D; ++v)
+          if (v < 4 || (v - 4) % D < d) bad |= nonfinite_bits(rec[q][v], false);
+      }
     double mr = mt;
 #pragma unroll
     for (int q = 0; q < FB; ++q)
@@ -297,6 +326,10 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
         }
       }
     }
+  }
+  {
+    const uint32_t wave_bad = __ballot(bad != 0u) != 0ull ? 1u : 0u;
+    if (lane == 0) s_bad[wv] = wave_bad;  // (published by the barrier below)
   }
   // wave level: common max, then fixed-pattern sums
   const double Mw = wave_max(mt);
@@ -355,13 +388,23 @@ __device__ void finalize_partials(const FinArgs& f, const T* __restrict__ part, 
     rec->var[lane] = var;
   }
   if (lane == 0) {
-    const double dlog = (M + log(S)) - log(swin_t);
+    // a usable step: finite partial sums, some positive weight now and
+    // before, no earlier failure (sticky until re-initialised)
+    uint32_t any_bad = 0u;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) any_bad |= s_bad[w];
+    const bool own = any_bad == 0u && S > 0.0 && swin_t > 0.0;
+    if (!own) atomicMin(&f.ctl->fail_t, f.t);
+    // steps reduced one at a time see an earlier failure here; deferred
+    // steps reduced together are fixed up in step order by the prefix pass
+    const bool ok = own && f.t < f.ctl->fail_t;
+    const double dlog = ok ? (M + log(S)) - log(swin_t) : 0.0;
     const double ln = ln0 + dlog;
     if (f.write_rec) {
       rec->t = f.t;
       if (f.k != kStageFromDevice) rec->stage = f.k;
       rec->radix = f.radix;
-      rec->valid = 1u;
+      rec->valid = ok ? 1u : 0u;
       rec->log_normaliser = f.multi ? 0.0 : ln;
       rec->ess = S * S / ((double)f.N * sw2_t);
       rec->max_log_weight = M;
@@ -426,9 +469,15 @@ template <typename T>
 __global__ void __launch_bounds__(64) pf_finalize_prefix(FinMulti fm) {
   if (threadIdx.x != 0) return;
   double ln = fm.ctl->log_norm;
+  const uint32_t fail_t = fm.ctl->fail_t;
   for (uint32_t i = 0; i < fm.n; ++i) {
-    ln += fm.ctl->dlog[i];
-    if (fm.n - 1u - i < fm.hist_cap) fm.hist[fm.steps[i].t % fm.hist_cap].log_normaliser = ln;
+    const bool ok = fm.steps[i].t < fail_t;
+    if (ok) ln += fm.ctl->dlog[i];
+    if (fm.n - 1u - i < fm.hist_cap) {
+      pf_estimate_t* r = fm.hist + fm.steps[i].t % fm.hist_cap;
+      r->log_normaliser = ln;
+      if (!ok) r->valid = 0u;
+    }
   }
   fm.ctl->log_norm = ln;
   fm.ctl->t = fm.steps[fm.n - 1u].t + 1u;
@@ -1417,6 +1466,15 @@ __global__ void __launch_bounds__(NT) pf_batch_finalize(BatchArgs ba) {
 // Global path, kernel 1: log-weights, tile max, tile inclusive CDF and
 // estimate partials. Every thread owns NLOC contiguous particles.
 // ---------------------------------------------------------------------------
+// Layout of the global path's coarse CDF levels (elements of the compute
+// type from the start of gcoarse): every 16th entry of the CDF (N / 16 of
+// them, then room for one run of 16 past the end), then, from a 16-element
+// boundary, 16 slots per weight tile for every 256th entry.
+__host__ __device__ constexpr uint64_t global_cc_offset(uint64_t N) { return ((N >> 4) + 31u) & ~(uint64_t)15u; }
+__host__ __device__ constexpr uint64_t global_coarse_elems(uint64_t N, uint64_t ntiles) {
+  return global_cc_offset(N) + 16u * ntiles;
+}
+
 template <int D, int MK, typename T, typename S, int NT, int PPT>
 __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   constexpr int NLOC = 2 * PPT;
@@ -1480,11 +1538,14 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     tot += wtot[i];
   }
   T c = woff + incl - run;
+  T* gcc = a.gcoarse + global_cc_offset(N);  // every 256th entry, 16 slots per tile
 #pragma unroll
   for (int e = 0; e < NLOC; ++e) {
     c += w[e];
     a.gcdf[base + e] = c;
-    if (((tid * NLOC + e) & 63) == 63) a.gcoarse[(base + e) >> 6] = c;
+    const uint32_t q = (uint32_t)(tid * NLOC + e);  // position in the tile
+    if ((q & 15u) == 15u) a.gcoarse[(base + e) >> 4] = c;
+    if ((q & 255u) == 255u) gcc[(size_t)tile * 16u + (q >> 8)] = c;
   }
   T* prt = a.part_out + (size_t)tile * PS;
   tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
@@ -1538,11 +1599,65 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   step_bookkeeping(a);
 }
 
-// Global path, kernel 3: inverse-CDF draw over the whole population (tile
-// prefix, then the tile's coarse CDF, then 64 fine entries), gather from
-// HBM, propagate, store.
+// Global path, kernel 3: inverse-CDF draw over the whole population, then
+// the gather from HBM, propagation and store. The draw finds the weight tile
+// by binary search of the FP64 tile prefix (in LDS), then the position in the
+// tile's FP32 CDF through two coarser levels written by kernel 1 (every 256th
+// and every 16th entry): each level reads one aligned run of 16 values and
+// counts those <= the target, which is the index of the first larger one
+// because the CDF does not decrease. A draw is three dependent 64-byte reads;
+// the 2 PPT draws of a thread go through the levels together, so their reads
+// are in flight at once. Consecutive threads take consecutive pairs, so the
+// monotone targets of systematic resampling read neighbouring runs and gather
+// neighbouring states.
+template <typename T, int ALIGN>
+__device__ __forceinline__ uint32_t count_le16(const T* run, T v, uint32_t n) {
+  const T* q = reinterpret_cast<const T*>(__builtin_assume_aligned(run, ALIGN));
+  T x[16];
+#pragma unroll
+  for (int k = 0; k < 16; ++k) x[k] = q[k];
+  uint32_t c = 0;
+#pragma unroll
+  for (int k = 0; k < 16; ++k) c += ((uint32_t)k < n && x[k] <= v) ? 1u : 0u;
+  return c;
+}
+
+// Particle index of the first CDF entry above lt[e] in weight tile b[e] (at
+// most the tile's last), for NP draws level by level: the every-256th level
+// (16 slots per tile, ncc = E / 256 of them used), the every-16th level, the
+// CDF itself. E = 2^lg_e >= 128 particles per tile.
+template <typename T, int NP>
+__device__ __forceinline__ void tile_positions(const T* gcc, const T* gcoarse, const T* gcdf, const uint32_t (&b)[NP],
+                                               const T (&lt)[NP], uint32_t lg_e, uint64_t (&aidx)[NP]) {
+  const uint32_t nb = 1u << (lg_e - 4u);        // 16-entry runs per tile
+  const uint32_t ncc = nb >> 4;                 // 256-entry runs per tile (0 below 256)
+  const uint32_t nb_run = nb < 16u ? nb : 16u;  // coarse entries in one level-B run
+  uint32_t j[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    uint32_t c = 0;
+    if (ncc) {
+      c = count_le16<T, 16 * sizeof(T)>(gcc + (size_t)b[e] * 16u, lt[e], ncc);
+      c = c < ncc ? c : ncc - 1u;
+    }
+    j[e] = c;
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const uint32_t c = count_le16<T, 16>(gcoarse + (size_t)b[e] * nb + 16u * j[e], lt[e], nb_run);
+    j[e] = 16u * j[e] + (c < nb_run ? c : nb_run - 1u);
+  }
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const uint64_t run0 = ((uint64_t)b[e] << lg_e) + 16u * j[e];
+    const uint32_t c = count_le16<T, 16 * sizeof(T)>(gcdf + run0, lt[e], 16u);
+    aidx[e] = run0 + (c < 16u ? c : 15u);
+  }
+}
+
 template <int D, int MK, typename T, typename S, int NT, int PPT>
 __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t tile_elems) {
+  constexpr int NP = 2 * PPT;
   extern __shared__ __align__(16) unsigned char smem[];
   double* spre = reinterpret_cast<double*>(smem);
   const uint32_t nt = a.ntiles;
@@ -1554,60 +1669,72 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
   const double* pre = pre_in_lds ? spre : a.gpre;
   const int d = (int)a.d;
   const uint64_t N = a.N;
+  const uint64_t npairs = N >> 1;
   const double total = a.gpre[nt];
   const uint32_t tau = a.t + 1u;
   const uint32_t lg_e = 31u - __clz(tile_elems);
-  const uint32_t ncoarse = tile_elems >> 6;
+  const T* gcc = a.gcoarse + global_cc_offset(N);
   double u0sys = 0.0;
   if (a.systematic) u0sys = word_uniform<double>(philox(0u, tau, 0u, a.sid, a.k0, a.k1).w0);
+  // the thread's pairs (clamped for the arithmetic; only valid ones store)
+  uint32_t pr[PPT];
+  T u[NP], z0[NP];
 #pragma unroll
   for (int it = 0; it < PPT; ++it) {
     const uint64_t p = ((uint64_t)blockIdx.x * PPT + it) * NT + threadIdx.x;
-    if (2 * p >= N) break;
-    T u[2], z[2][D], xo[2][D];
+    pr[it] = (uint32_t)(p < npairs ? p : npairs - 1u);
+    pair_block0<T>(pr[it], tau, a.sid, a.k0, a.k1, u[2 * it], u[2 * it + 1], z0[2 * it], z0[2 * it + 1]);
+  }
+  double target[NP];
 #pragma unroll
-    for (int j = 0; j < D; ++j) z[0][j] = z[1][j] = 0;
-    pair_randoms<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, u[0], u[1], z[0], z[1]);
-    uint32_t anc[2];
+  for (int e = 0; e < NP; ++e) {
+    const uint64_t i = 2ull * pr[e >> 1] + (uint64_t)(e & 1);
+    target[e] = a.systematic ? ((double)i + u0sys) * total / (double)N : (double)u[e] * total;
+  }
+  // tile: number of tile prefixes P_1..P_nt that are <= target
+  uint32_t b[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) b[e] = 0;
+  for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < NP; ++e)
+      if (b[e] + s <= nt && pre[b[e] + s] <= target[e]) b[e] += s;
+  }
+  // beyond the last tile (target at the total): the last tile's last entry
+  T lt[NP];
+#pragma unroll
+  for (int e = 0; e < NP; ++e) {
+    const bool past = b[e] >= nt;
+    b[e] = past ? nt - 1u : b[e];
+    lt[e] = past ? (T)INFINITY : (T)((target[e] - pre[b[e]]) / a.gscale[b[e]]);
+  }
+  uint64_t aidx[NP];
+  tile_positions<T, NP>(gcc, a.gcoarse, a.gcdf, b, lt, lg_e, aidx);
+  // gather, propagate, store (one pair at a time)
+#pragma unroll
+  for (int it = 0; it < PPT; ++it) {
+    const uint64_t p = ((uint64_t)blockIdx.x * PPT + it) * NT + threadIdx.x;
+    if (p >= npairs) continue;
+    T z[2][D], xo[2][D];
+#pragma unroll
+    for (int jj = 0; jj < D; ++jj) z[0][jj] = z[1][jj] = 0;
+    z[0][0] = z0[2 * it];
+    z[1][0] = z0[2 * it + 1];
+    pair_normals_rest<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
 #pragma unroll
     for (int e = 0; e < 2; ++e) {
-      const uint64_t i = 2 * p + e;
-      const double target = a.systematic ? ((double)i + u0sys) * total / (double)N
-                                         : (double)u[e] * total;
-      // tile: number of tile prefixes P_1..P_nt that are <= target
-      uint32_t b = 0;
-      for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
-        if (b + s <= nt && pre[b + s] <= target) b += s;
-      }
-      uint64_t a_idx;
-      if (b >= nt) {
-        a_idx = N - 1;
-      } else {
-        const T lt = (T)((target - pre[b]) / a.gscale[b]);
-        const T* co = a.gcoarse + (size_t)b * ncoarse;
-        uint32_t ch = 0;
-        for (uint32_t s = ncoarse >> 1; s >= 1u; s >>= 1)
-          if (co[ch + s - 1] <= lt) ch += s;
-        if (ch >= ncoarse) ch = ncoarse - 1;
-        const T* fine = a.gcdf + ((uint64_t)b << lg_e) + ((uint64_t)ch << 6);
-        uint32_t pos = 0;
-        for (uint32_t s = 32; s >= 1u; s >>= 1)
-          if (fine[pos + s - 1] <= lt) pos += s;
-        a_idx = ((uint64_t)b << lg_e) + ((uint64_t)ch << 6) + pos;
-      }
-      anc[e] = (uint32_t)a_idx;
       T xh[D];
 #pragma unroll
-      for (int j = 0; j < D; ++j)
-        xh[j] = (j < d) ? Single<S, T>::load(a.x_in + (size_t)j * N + a_idx) : (T)0;
+      for (int jj = 0; jj < D; ++jj)
+        xh[jj] = (jj < d) ? Single<S, T>::load(a.x_in + (size_t)jj * N + aidx[2 * it + e]) : (T)0;
       Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
     }
 #pragma unroll
-    for (int j = 0; j < D; ++j)
-      if (j < d) Pair<S, T>::store(a.x_out + (size_t)j * N + 2 * p, xo[0][j], xo[1][j]);
+    for (int jj = 0; jj < D; ++jj)
+      if (jj < d) Pair<S, T>::store(a.x_out + (size_t)jj * N + 2 * p, xo[0][jj], xo[1][jj]);
     if (a.anc) {
-      a.anc[2 * p] = anc[0];
-      a.anc[2 * p + 1] = anc[1];
+      a.anc[2 * p] = (uint32_t)aidx[2 * it];
+      a.anc[2 * p + 1] = (uint32_t)aidx[2 * it + 1];
     }
   }
 }

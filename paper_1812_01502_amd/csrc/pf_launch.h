@@ -61,7 +61,7 @@ constexpr int ppt_wave(int D) { return D <= 2 ? 4 : 1; }
 constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 : 1)); }
 // Pairs per thread of the global weight kernel (256 threads).
 constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
-constexpr int kDrawPPT = 4;
+constexpr int kDrawPPT = 2;
 
 template <typename K> static hipError_t ensure_lds(K* kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;

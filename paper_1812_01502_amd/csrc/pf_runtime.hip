@@ -2,6 +2,8 @@
 // buffers, kernel launches, state access and error handling.
 #include <hip/hip_runtime.h>
 
+#include <cstddef>
+
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -32,6 +34,9 @@ DevAllocator current_allocator() {
   std::lock_guard<std::mutex> lk(g_alloc_mu);
   return g_alloc;
 }
+// The message pf_last_error(NULL) returns (failed creates and calls without
+// a handle).
+void set_create_error(const char* msg) { g_create_error = msg; }
 }  // namespace pfh
 
 struct pf_handle {
@@ -85,6 +90,7 @@ struct pf_handle {
   size_t ad_lds = 0;
   uint64_t bytes = 0;
   pf_status sticky = PF_OK;
+  bool numeric = false;  // the device flagged unusable weights (sticky until re-initialised)
   std::string err;
   DevAllocator dalloc_fn;    // the allocator current at create time
   std::vector<void*> allocs;
@@ -639,6 +645,9 @@ pf_status do_step(pf_handle* h, const double* y_host, const void* y_dev) {
   }
 }
 
+}  // namespace
+
+namespace pfh {
 // Stage plan of the butterfly path (radix < N) into out[0 .. *n_out): mixed
 // radix, tile shape, LDS. The island filter's within-island launch is one
 // stage of radix M and stride 1 (island = true, radix = M). No heap memory,
@@ -720,7 +729,7 @@ pf_status plan_butterfly(uint64_t N, uint64_t radix, int D, int d, size_t tsz, b
     sp.C = E / sp.r;
     sp.log2C = ilog2(sp.C);
     sp.ntiles = (uint32_t)(N / E);
-    sp.pad = choose_pad(sp.r, sp.C, sp.log2R, sp.nt);
+    sp.pad = choose_pad_eval(sp.r, sp.C, sp.log2R, sp.nt);
     sp.xrow = state_row_pitch(sp.C, sp.log2R, sp.log2C);
     // the within-island launch of the island filter stages no states
     sp.lds = tile_lds_bytes(island ? 0 : d, D, tsz, sp.r, sp.C, sp.pad, sp.nt, sp.blockpath != 0, sp.xrow);
@@ -733,6 +742,9 @@ pf_status plan_butterfly(uint64_t N, uint64_t radix, int D, int d, size_t tsz, b
   *n_out = nst;
   return PF_OK;
 }
+}  // namespace pfh
+
+namespace {
 
 pf_status plan_stages(pf_handle* h) {
   const uint64_t N = h->N;
@@ -776,6 +788,24 @@ void release(pf_handle* h) {
 }
 
 bool poisoned(pf_handle* h) { return h->sticky != PF_OK; }
+
+pf_status numeric_fail(pf_handle* h) {
+  return fail(h, PF_E_NUMERIC,
+              "a step's weights were not usable (non-finite, or none positive); pf_reset, pf_set_state "
+              "or pf_load start the filter again");
+}
+
+// After a synchronisation: the device's sticky flag of unusable weights.
+pf_status check_numeric(pf_handle* h) {
+  if (!h->numeric) {
+    uint32_t fl = 0;
+    hipError_t e = hipMemcpy(&fl, reinterpret_cast<const char*>(h->ctl) + offsetof(Ctl, fail_t), sizeof(fl),
+                             hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(h, e, "control copy");
+    h->numeric = fl != kNoFail;
+  }
+  return h->numeric ? numeric_fail(h) : PF_OK;
+}
 
 }  // namespace
 
@@ -970,7 +1000,8 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   }
   if (h->global) {
     if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz)) != PF_OK) return bail(s);
-    if ((s = dalloc(h, &h->gcoarse, (size_t)(N / 64 + 1) * h->tsz)) != PF_OK) return bail(s);
+    if ((s = dalloc(h, &h->gcoarse, (size_t)global_coarse_elems(N, h->g_ntiles) * h->tsz)) != PF_OK)
+      return bail(s);
     if ((s = dalloc(h, &p, (size_t)(h->g_ntiles + 1) * 8)) != PF_OK) return bail(s);
     h->gpre = reinterpret_cast<double*>(p);
     if ((s = dalloc(h, &p, (size_t)h->g_ntiles * 8)) != PF_OK) return bail(s);
@@ -995,6 +1026,7 @@ pf_status pf_reset(pf_handle* h) {
   if (!h) return PF_E_INVALID;
   if (poisoned(h)) return PF_E_STATE;
   h->cur = 0;
+  h->numeric = false;  // the initialisation clears the device flag
   return do_init(h);
 }
 
@@ -1003,6 +1035,7 @@ pf_status pf_step(pf_handle* h, const double* y_host) {
   if (poisoned(h)) return PF_E_STATE;
   if (!y_host) return fail(h, PF_E_INVALID, "y is NULL");
   if (!finite_all(y_host, h->d)) return fail(h, PF_E_NUMERIC, "non-finite observation");
+  if (h->numeric) return numeric_fail(h);
   return do_step(h, y_host, nullptr);
 }
 
@@ -1011,6 +1044,7 @@ pf_status pf_run(pf_handle* h, const void* y_dev, uint32_t n_steps, uint64_t y_s
   if (poisoned(h)) return PF_E_STATE;
   if (!y_dev) return fail(h, PF_E_INVALID, "y_dev is NULL");
   if (y_stride < (uint64_t)h->d) return fail(h, PF_E_INVALID, "y_stride < d");
+  if (h->numeric) return numeric_fail(h);
   if (n_steps == 0) return PF_OK;
   const char* yb = reinterpret_cast<const char*>(y_dev);
   hipGraph_t graph = nullptr;
@@ -1070,7 +1104,7 @@ pf_status pf_estimate(pf_handle* h, pf_estimate_t* out) {
   const uint64_t slot = (h->t - 1) % h->hist_cap;
   hipError_t e = hipMemcpy(out, h->hist + slot, sizeof(*out), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "estimate copy");
-  return PF_OK;
+  return check_numeric(h);
 }
 
 pf_status pf_history(pf_handle* h, pf_estimate_t* out, uint32_t n_max, uint32_t* n_out) {
@@ -1088,7 +1122,7 @@ pf_status pf_history(pf_handle* h, pf_estimate_t* out, uint32_t n_max, uint32_t*
     out[i] = all[t % h->hist_cap];
   }
   *n_out = (uint32_t)n;
-  return PF_OK;
+  return check_numeric(h);
 }
 
 pf_status pf_get_state(pf_handle* h, void* x_host, void* logw_host, uint32_t* t_out, double* log_norm) {
@@ -1147,6 +1181,8 @@ pf_status pf_set_state(pf_handle* h, const void* x_host, const void* logw_host, 
   if (e != hipSuccess) return hip_fail(h, e, "control copy");
   c.log_norm = log_norm;
   c.ad_active = c.ad_stage = c.ad_run = c.ad_next = 0u;  // ESS-gated stages start at stage 0
+  c.fail_t = kNoFail;
+  h->numeric = false;
   for (int i = 0; i < kOffEntries; ++i) c.offs[i] = ord_encode(-INFINITY);
   c.offs[(t % kOffRing) * kOffSlots * kOffStride] = ord_encode(0.0);
   c.t = t;
@@ -1252,6 +1288,8 @@ pf_status pf_load(pf_handle* h, const void* buf, uint64_t len) {
   e = hipMemcpy(&c, h->ctl, sizeof(c), hipMemcpyDeviceToHost);
   if (e != hipSuccess) return hip_fail(h, e, "control copy");
   c.log_norm = hd.log_norm;
+  c.fail_t = kNoFail;
+  h->numeric = false;
   c.t = (uint32_t)hd.t;
   c.ad_active = c.ad_stage = c.ad_run = 0u;
   c.ad_next = hd.next_stage < h->stages.size() ? hd.next_stage : 0u;

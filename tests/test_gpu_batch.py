@@ -97,8 +97,37 @@ def test_batch_one_step_against_oracle():
     new log-weights and states (where the oracle's draw margin exceeds the
     tolerance) must match the FP64 oracle."""
     spec = _mix()
-    models = [m for m, _, _ in spec]
     b = _batch(spec)
+    _oracle_steps(b, spec)
+    b.close()
+
+
+def test_batch_autotuned_classes_of_the_batched_workload_against_oracle():
+    """The batched workload's shapes: filters of d = 1, 4 and 16 at the
+    largest N of the workload (2^16) beside ones at the smallest (2^10),
+    radix and tile chosen by the autotuner (one class per dimension, as in
+    the benchmark); each filter one teacher-forced step against the oracle
+    at its widest stride."""
+    from paper_1812_01502_amd import BatchFilter
+    shapes = [(1, 1 << 16), (4, 1 << 16), (16, 1 << 16), (1, 1 << 10), (4, 1 << 10), (16, 1 << 10)]
+    models = [W.random_stable_lg(d, 4100 + i) for i, (d, _) in enumerate(shapes)]
+    Ns = [n for _, n in shapes]
+    b = BatchFilter(models, Ns, [0] * len(shapes), [100 + i for i in range(len(shapes))])
+    chosen = sorted({(t["dim"], t["radix"], 512 * t["ppt"]) for t in b.tuning() if t["chosen"]})
+    log(f"[case] autotuned batch: (d, radix, tile) = {chosen}")
+    spec = []
+    for i, m in enumerate(models):
+        info = b.info(i)
+        spec.append((m, Ns[i], info["stages"][0]))
+        log(f"   filter {i}: d={m.d} N={Ns[i]} stages={info['stages']} tile={info['tile']}")
+    _oracle_steps(b, spec)
+    b.close()
+
+
+def _oracle_steps(b, spec):
+    """One teacher-forced step of every filter of batch ``b`` (spec: model,
+    N, radix per filter; seeds 100 + i, stream ids i) against the oracle."""
+    import torch
     tol = tolerances("f32")
     for i, (m, N, r) in enumerate(spec):
         orc = ButterflyOracle(m, N, r, seed=100 + i, stream_id=i)
@@ -115,7 +144,6 @@ def test_batch_one_step_against_oracle():
         ypack[b.y_offsets[i]:b.y_offsets[i] + m.d] = ys[t]
         active = np.zeros(b.n, dtype=np.uint8)
         active[i] = 1
-        import torch
         yd = _dev(ypack, torch.float32)
         ad = _dev(active, torch.uint8)
         b.step(yd.data_ptr(), ad.data_ptr())
@@ -135,7 +163,6 @@ def test_batch_one_step_against_oracle():
         lim = tol["x_atol"] + tol["x_rtol"] * np.abs(st1.x[sure])
         assert np.all(err <= lim), (i, float(np.max(err - lim)))
         log(f"   ok near={int(np.sum(~sure))} max_dx={float(np.max(err)):.2e}")
-    b.close()
 
 
 def test_active_mask_and_alone_vs_mix():

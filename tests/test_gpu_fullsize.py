@@ -57,3 +57,48 @@ def test_sv_n2p24_radix64_and_bf16():
     """SV, N = 2^24, radix 64 (four stages of 64), FP32 and BF16 states."""
     _run("c3", 1 << 24, 64, steps=[3])
     _run("c3", 1 << 24, 64, steps=[1], dtype="bf16")
+
+
+def test_sv_n2p24_radix32_first_and_top_stage():
+    """SV, N = 2^24, radix 32 (stages 32, 32, 32, 32, 16): the stride-1 stage
+    and the radix-16 stage at stride 2^20."""
+    _run("c3", 1 << 24, 32, steps=[0, 4])
+
+
+def test_sv_n2p24_radix256():
+    """SV, N = 2^24, radix 256 (stages 256, 256, 256): the block path at
+    stride 256."""
+    _run("c3", 1 << 24, 256, steps=[1])
+
+
+def test_sv_n2p24_global_f32_and_bf16():
+    """SV, N = 2^24, the global bootstrap filter (r = N), FP32 and BF16
+    states."""
+    _run("c3", 1 << 24, 1 << 24, steps=[0, 1])
+    _run("c3", 1 << 24, 1 << 24, steps=[1], dtype="bf16")
+
+
+def test_sv_n2p24_radix1024_bf16():
+    """SV, N = 2^24, radix 1024 with BF16 states: the block path at stride
+    1024."""
+    _run("c3", 1 << 24, 1024, steps=[1], dtype="bf16")
+
+
+def test_sv_n2p24_island_m4096():
+    """The island filter at its benchmarked shape: SV, N = 2^24 in 4096
+    islands of 4096 (within-island launch of 1024-thread tiles, island
+    stages in two launches, LDS-staged gather), one teacher-forced step."""
+    from oracle import IslandOracle
+    from paper_1812_01502_amd import Filter
+    from tests.gpu_util import compare_island_step
+    cfg = W.config("c3")
+    model = cfg["model"]
+    N, M = 1 << 24, 4096
+    orc = IslandOracle(model, N, M, seed=23, stream_id=2)
+    _, ys = W.simulate(model, 2, seed=cfg["seed_obs"])
+    st = orc.init()
+    log(f"[case] island full size SV N={N} M={M}")
+    flt = Filter(model, N, 2, seed=23, stream_id=2, keep_ancestors=True, island=M)
+    r = compare_island_step(flt, orc, st.x, np.zeros(N), 0, ys[0], label="sv-2^24-M4096")
+    log(f"   ok sure={r['sure']:.4f} flips={r['flips']} max_dx={r['max_dx']:.2e}")
+    flt.close()

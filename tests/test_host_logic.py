@@ -1,7 +1,8 @@
-"""Host-side logic that needs no GPU: serving pool sizing."""
+"""Host-side logic that needs no GPU: serving admission and footprints, and
+kernel-header helpers compiled for the host."""
 import pytest
 
-from paper_1812_01502_amd.serving import CTL_BYTES, PARAM_BYTES, slot_footprint, slots_for_budget
+from paper_1812_01502_amd.serving import CTL_BYTES, PARAM_BYTES, StreamRequest, plan_admission, slot_footprint
 
 
 def test_control_and_parameter_sizes_match_the_device_structs():
@@ -39,24 +40,59 @@ def test_control_and_parameter_sizes_match_the_device_structs():
 
 
 def test_slot_footprint_counts_every_buffer():
-    # states (2 buffers x d planes) + log-weights (2 buffers) + partial records
-    # + control block + model parameters + record
-    assert slot_footprint(1, 4096) == 2 * 4096 * 4 + 2 * 4096 * 4 + 8 * 7 * 4 + CTL_BYTES + PARAM_BYTES + 304
+    # states (2 buffers x d planes) + log-weights (2 buffers) + partial records,
+    # each rounded to 64 floats as the library allocates them, + control block
+    # + model parameters + record
+    assert slot_footprint(1, 4096) == 4 * (2 * 4096 + 2 * 4096 + 64) + CTL_BYTES + PARAM_BYTES + 304
     assert slot_footprint(16, 1 << 20) > slot_footprint(4, 1 << 20) > slot_footprint(1, 1 << 20)
 
 
-@pytest.mark.parametrize("budget", [1 << 26, 1 << 30, 24 << 30])
-def test_slots_for_budget_fits(budget):
-    dims = {"sv": 1, "lg4": 4}
-    shapes = {("sv", 4096): 1.0, ("lg4", 1 << 16): 1.0, ("lg4", 1 << 20): 2.0}
-    cnt = slots_for_budget(shapes, dims, budget)
-    used = sum(slot_footprint(dims[m], n) * c for (m, n), c in cnt.items())
-    assert all(c >= 1 for c in cnt.values())
-    # each pool stays within its share (pools of one slot may exceed a tiny budget)
-    for (m, n), c in cnt.items():
-        share = budget * shapes[(m, n)] / sum(shapes.values())
-        assert c == 1 or c * slot_footprint(dims[m], n) <= share
-    assert used <= budget or min(cnt.values()) == 1
+def _req(i, model, n):
+    return StreamRequest(stream_id=i, model=model, n_particles=n, observations=None)
+
+
+def _plan(waiting, shapes, nbytes, budget, fps, free=None):
+    s_shape = list(shapes)
+    s_bytes = list(nbytes)
+    free = list(range(len(shapes))) if free is None else free
+    out = plan_admission(waiting, free, s_shape, s_bytes, budget,
+                         lambda r: fps.get((r.model, r.n_particles)))
+    return out, s_shape, s_bytes
+
+
+def test_admission_by_footprint_any_shape():
+    """Streams of any shape are admitted while their footprints fit the
+    budget; the rest wait; one larger than the budget is rejected."""
+    fps = {("sv", 4096): 100, ("lg4", 1 << 20): 700, ("lg16", 1 << 16): 250, ("sv", 1 << 24): 5000}
+    w = [_req(0, "sv", 4096), _req(1, "lg4", 1 << 20), _req(2, "lg16", 1 << 16), _req(3, "sv", 1 << 24),
+         _req(4, "sv", 4096), _req(5, "nope", 4096)]
+    (bind, rel, still, rej), shape, nb = _plan(w, [None] * 4, [0] * 4, 1000, fps)
+    assert [r.stream_id for _, r in bind] == [0, 1, 4]      # 100 + 700 + 100 <= 1000; 250 waits
+    assert [r.stream_id for r in still] == [2]
+    assert sorted(r.stream_id for r, _ in rej) == [3, 5]
+    assert sum(nb) == 900 and rel == []
+    assert all(shape[s] == (r.model, r.n_particles) for s, r in bind)
+
+
+def test_admission_reuses_and_releases_free_slots():
+    """A free slot already holding the stream's shape is reused without new
+    memory; otherwise the memory of free slots is given back (largest first)
+    until the new stream fits; active slots are never touched."""
+    fps = {("sv", 4096): 100, ("lg4", 1 << 20): 700}
+    shapes = [("sv", 4096), ("lg4", 1 << 20), ("sv", 4096), None]
+    nbytes = [100, 700, 100, 0]
+    # slot 2 is active (not free); the budget is full but for 100 bytes
+    (bind, rel, still, rej), shape, nb = _plan([_req(0, "sv", 4096)], shapes, nbytes, 1000, fps, free=[0, 1, 3])
+    assert bind[0][0] == 0 and rel == [] and nb == [100, 700, 100, 0]
+    (bind, rel, still, rej), shape, nb = _plan([_req(1, "lg4", 1 << 20), _req(2, "lg4", 1 << 20)],
+                                              shapes, nbytes, 1000, fps, free=[0, 3])
+    # slot 1 is busy: the first lg4 stream needs 700 with 100 left -> slot 0's
+    # 100 bytes are not enough, so it waits; so does the second
+    assert bind == [] and [r.stream_id for r in still] == [1, 2]
+    (bind, rel, still, rej), shape, nb = _plan([_req(1, "lg4", 1 << 20)], shapes, nbytes, 1500, fps,
+                                              free=[0, 3])
+    assert bind[0][0] == 3 and rel == [0] and nb == [0, 700, 100, 700] and shape[0] is None
+    assert sum(nb) <= 1500
 
 
 def test_tile_coordinates_cover_every_particle_once():
@@ -190,3 +226,95 @@ int main() {
         shutil.rmtree(d, ignore_errors=True)
     cases, bad = int(out[0]), int(out[1])
     assert cases == 6 * 200 * 256 and bad == 0
+
+
+def test_global_draw_tile_positions():
+    """The position search of the global path's draw (tile_positions), built
+    for the host from the kernel header with AddressSanitizer: on tiles whose
+    coarse levels hold every 16th and every 256th entry of the tile CDF in the
+    device layout (global_cc_offset), it returns what a plain binary search
+    of the tile CDF returns (the number of entries <= target, at most E - 1)
+    for every tile size the runtime uses (E = 128 .. 4096), with zero weights,
+    ties, targets equal to an entry, below the first and above the last; no
+    read leaves the arrays as the runtime sizes them."""
+    import os
+    import re
+    import shutil
+    import subprocess
+    import tempfile
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ker = open(os.path.join(root, "paper_1812_01502_amd", "csrc", "pf_kernels.h")).read()
+    parts = [re.search(r"__host__ __device__ constexpr uint64_t global_cc_offset\(.*?\n", ker).group(0),
+             re.search(r"__host__ __device__ constexpr uint64_t global_coarse_elems\(.*?\n}\n", ker, re.S).group(0),
+             re.search(r"template <typename T, int ALIGN>\n__device__ __forceinline__ uint32_t count_le16\(.*?\n}\n",
+                       ker, re.S).group(0),
+             re.search(r"template <typename T, int NP>\n__device__ __forceinline__ void tile_positions\(.*?\n}\n",
+                       ker, re.S).group(0)]
+    src = ("#define __device__\n#define __host__\n#define __forceinline__ inline\n"
+           "#include <cstdint>\n#include <cstddef>\n#include <cstdio>\n#include <random>\n#include <vector>\n"
+           "#include <cmath>\n" + "\n".join(parts) + r'''
+long check(uint32_t lg_e, uint32_t nt, std::mt19937& g, long& cases) {
+  const uint32_t E = 1u << lg_e;
+  const uint64_t N = (uint64_t)E * nt;
+  long bad = 0;
+  for (int trial = 0; trial < 40; ++trial) {
+    std::vector<float> cdf(N), coarse(global_coarse_elems(N, nt));
+    float* cc = coarse.data() + global_cc_offset(N);
+    for (uint32_t b = 0; b < nt; ++b) {
+      float acc = 0.f;
+      for (uint32_t q = 0; q < E; ++q) {
+        const uint32_t kind = g() % 8u;
+        acc += kind < 2 ? 0.f : (kind == 2 ? 1.f : (float)(g() % 1000u) * 1e-3f);
+        const uint64_t i = (uint64_t)b * E + q;
+        cdf[i] = acc;
+        if ((q & 15u) == 15u) coarse[i >> 4] = acc;
+        if ((q & 255u) == 255u) cc[(size_t)b * 16u + (q >> 8)] = acc;
+      }
+    }
+    for (int k = 0; k < 64; ++k) {
+      constexpr int NP = 4;
+      uint32_t bb[NP];
+      float lt[NP];
+      uint64_t want[NP], got[NP];
+      for (int e = 0; e < NP; ++e) {
+        bb[e] = g() % nt;
+        const float* t = cdf.data() + (uint64_t)bb[e] * E;
+        const uint32_t sel = g() % 5u;
+        lt[e] = sel == 0 ? t[g() % E] : sel == 1 ? t[E - 1] * (float)(g() % 1000001u) * 1e-6f
+              : sel == 2 ? -1.f : sel == 3 ? t[E - 1] + 1.f : INFINITY;
+        uint32_t pos = 0;
+        for (uint32_t s = E >> 1; s >= 1u; s >>= 1)
+          if (t[pos + s - 1u] <= lt[e]) pos += s;
+        want[e] = (uint64_t)bb[e] * E + pos;
+      }
+      tile_positions<float, NP>(cc, coarse.data(), cdf.data(), bb, lt, lg_e, got);
+      for (int e = 0; e < NP; ++e) {
+        ++cases;
+        if (got[e] != want[e]) ++bad;
+      }
+    }
+  }
+  return bad;
+}
+int main() {
+  std::mt19937 g(11);
+  long cases = 0, bad = 0;
+  for (uint32_t lg_e : {7u, 9u, 10u, 11u, 12u})
+    for (uint32_t nt : {1u, 3u}) bad += check(lg_e, nt, g, cases);
+  printf("%ld %ld\n", cases, bad);
+  return 0;
+}
+''')
+    d = tempfile.mkdtemp()
+    try:
+        open(os.path.join(d, "s.cpp"), "w").write(src)
+        subprocess.run([cxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        os.path.join(d, "s.cpp"), "-o", os.path.join(d, "s")], check=True)
+        out = subprocess.run([os.path.join(d, "s")], capture_output=True, text=True, check=True).stdout.split()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    cases, bad = int(out[0]), int(out[1])
+    assert cases == 5 * 2 * 40 * 64 * 4 and bad == 0, (cases, bad)
