@@ -358,14 +358,15 @@ def profile_mode(args, L: Legs):
     """One filter's warm-up and timed steps (for rocprofv3), then a plain copy
     of known size (counter calibration)."""
     import torch
+    rs = args.resampler
     if args.profile_island:
-        flt = L.make(2, args.dtype, island=island_size(args, L.N))
+        flt = L.make(2, args.dtype, island=island_size(args, L.N), resampler=rs)
     elif args.profile_adaptive:
-        flt = L.make(args.radix, args.dtype, ess_threshold=0.5)
+        flt = L.make(args.radix, args.dtype, ess_threshold=0.5, resampler=rs)
     elif args.profile_global:
-        flt = L.make(L.N, args.dtype)
+        flt = L.make(L.N, args.dtype, resampler=rs)
     else:
-        flt = L.make(args.radix, args.dtype)
+        flt = L.make(args.radix, args.dtype, resampler=rs)
     wall, ev_s = L.time(flt, args.dtype)
     flt.close()
     src = torch.empty(1 << 27, dtype=torch.float32, device="cuda")   # 512 MiB
@@ -386,6 +387,8 @@ def main():
                     help="untimed steps of every filter before its timed steps")
     ap.add_argument("--radix", type=int, default=64, help="radix of the headline (and of --mode profile)")
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32", help="--mode profile: state storage")
+    ap.add_argument("--resampler", choices=["multinomial", "systematic"], default="multinomial",
+                    help="--mode profile: resampler")
     ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["sv", "lg8"], default="sv",
@@ -456,6 +459,10 @@ def main():
         sv["global_bpf"][dt] = safe(lambda dt=dt: L3.leg(N, dt)[0])
         for r in (32, 256, 1024) + ((64,) if dt == "bf16" else ()):
             sv["per_radix"][f"{r} {dt}"] = safe(lambda r=r, dt=dt: L3.leg(r, dt)[0])
+    # systematic resampling: monotone draws, so the global filter's reads of
+    # the CDF and its gather are near-sequential
+    sv["systematic"] = {"64 f32": safe(lambda: L3.leg(64, "f32", resampler="systematic")[0]),
+                        "global f32": safe(lambda: L3.leg(N, "f32", resampler="systematic")[0])}
     sv.update(variants(L3, 64, args.island or 4096))
 
     # -- the headline: radix 64, FP32 ------------------------------------------

@@ -1554,16 +1554,27 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
 }
 
 // Global path, kernel 2 (one block): tile prefix in FP64; every new
-// log-weight is equal, so the next offset is 0.
+// log-weight is equal, so the next offset is 0. Each thread owns a
+// contiguous run of tiles and issues the loads of up to 16 of them before it
+// uses any.
 template <int D, typename T, typename S, int NT>
 __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   __shared__ double sd[NT];
   constexpr int PS = partial_stride(D);
+  constexpr uint32_t CH = 16;
   const T* part = a.part_out;
   const uint32_t nt = a.ntiles;
   const int tid = threadIdx.x;
+  const uint32_t per = (nt + NT - 1) / NT;
+  const uint32_t b0 = tid * per, b1 = min(nt, b0 + per);
   double m = -INFINITY;
-  for (uint32_t b = tid; b < nt; b += NT) m = fmax(m, (double)part[(size_t)b * PS]);
+  for (uint32_t c = b0; c < b1; c += CH) {
+    T mv[CH];
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) mv[k] = c + k < b1 ? part[(size_t)(c + k) * PS] : (T)-INFINITY;
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) m = fmax(m, (double)mv[k]);
+  }
   sd[tid] = m;
   __syncthreads();
   for (int s = NT / 2; s > 0; s >>= 1) {
@@ -1572,14 +1583,24 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   }
   const double M = sd[0];
   __syncthreads();
-  // exclusive prefix of T_b = S_b e^{m_b - M}: contiguous chunks per thread
-  const uint32_t per = (nt + NT - 1) / NT;
-  const uint32_t b0 = tid * per, b1 = min(nt, b0 + per);
+  // exclusive prefix of T_b = S_b e^{m_b - M}: contiguous runs per thread
   double loc = 0.0;
-  for (uint32_t b = b0; b < b1; ++b) {
-    const double e = exp((double)part[(size_t)b * PS] - M);
-    a.gscale[b] = e;
-    loc += e * (double)part[(size_t)b * PS + 1];
+  for (uint32_t c = b0; c < b1; c += CH) {
+    T mv[CH], sv[CH];
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) {
+      const size_t b = (size_t)(c + k < b1 ? c + k : b0) * PS;
+      mv[k] = part[b];
+      sv[k] = part[b + 1];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) {
+      if (c + k < b1) {
+        const double e = exp((double)mv[k] - M);
+        a.gscale[c + k] = e;
+        loc += e * (double)sv[k];
+      }
+    }
   }
   sd[tid] = loc;
   __syncthreads();
@@ -1590,9 +1611,22 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     __syncthreads();
   }
   double run = sd[tid] - loc;
-  for (uint32_t b = b0; b < b1; ++b) {
-    a.gpre[b] = run;
-    run += a.gscale[b] * (double)part[(size_t)b * PS + 1];
+  for (uint32_t c = b0; c < b1; c += CH) {
+    T sv[CH];
+    double ev[CH];
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) {
+      const uint32_t b = c + k < b1 ? c + k : b0;
+      sv[k] = part[(size_t)b * PS + 1];
+      ev[k] = a.gscale[b];
+    }
+#pragma unroll
+    for (uint32_t k = 0; k < CH; ++k) {
+      if (c + k < b1) {
+        a.gpre[c + k] = run;
+        run += ev[k] * (double)sv[k];
+      }
+    }
   }
   if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
   if (tid == 0) *off_slot(a.ctl, a.u + 1, 0) = ord_encode(0.0);
@@ -1656,7 +1690,7 @@ __device__ __forceinline__ void tile_positions(const T* gcc, const T* gcoarse, c
 }
 
 template <int D, int MK, typename T, typename S, int NT, int PPT>
-__global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t tile_elems) {
+__global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t tile_elems, uint32_t nchunks) {
   constexpr int NP = 2 * PPT;
   extern __shared__ __align__(16) unsigned char smem[];
   double* spre = reinterpret_cast<double*>(smem);
@@ -1676,65 +1710,69 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
   const T* gcc = a.gcoarse + global_cc_offset(N);
   double u0sys = 0.0;
   if (a.systematic) u0sys = word_uniform<double>(philox(0u, tau, 0u, a.sid, a.k0, a.k1).w0);
-  // the thread's pairs (clamped for the arithmetic; only valid ones store)
-  uint32_t pr[PPT];
-  T u[NP], z0[NP];
+  // a persistent grid: block b takes chunks b, b + gridDim.x, ... of NT PPT
+  // pairs, so the tile prefix is staged in LDS once per block
+  for (uint32_t chunk = blockIdx.x; chunk < nchunks; chunk += gridDim.x) {
+    // the thread's pairs (clamped for the arithmetic; only valid ones store)
+    uint32_t pr[PPT];
+    T u[NP], z0[NP];
 #pragma unroll
-  for (int it = 0; it < PPT; ++it) {
-    const uint64_t p = ((uint64_t)blockIdx.x * PPT + it) * NT + threadIdx.x;
-    pr[it] = (uint32_t)(p < npairs ? p : npairs - 1u);
-    pair_block0<T>(pr[it], tau, a.sid, a.k0, a.k1, u[2 * it], u[2 * it + 1], z0[2 * it], z0[2 * it + 1]);
-  }
-  double target[NP];
+    for (int it = 0; it < PPT; ++it) {
+      const uint64_t p = ((uint64_t)chunk * PPT + it) * NT + threadIdx.x;
+      pr[it] = (uint32_t)(p < npairs ? p : npairs - 1u);
+      pair_block0<T>(pr[it], tau, a.sid, a.k0, a.k1, u[2 * it], u[2 * it + 1], z0[2 * it], z0[2 * it + 1]);
+    }
+    double target[NP];
 #pragma unroll
-  for (int e = 0; e < NP; ++e) {
-    const uint64_t i = 2ull * pr[e >> 1] + (uint64_t)(e & 1);
-    target[e] = a.systematic ? ((double)i + u0sys) * total / (double)N : (double)u[e] * total;
-  }
-  // tile: number of tile prefixes P_1..P_nt that are <= target
-  uint32_t b[NP];
+    for (int e = 0; e < NP; ++e) {
+      const uint64_t i = 2ull * pr[e >> 1] + (uint64_t)(e & 1);
+      target[e] = a.systematic ? ((double)i + u0sys) * total / (double)N : (double)u[e] * total;
+    }
+    // tile: number of tile prefixes P_1..P_nt that are <= target
+    uint32_t b[NP];
 #pragma unroll
-  for (int e = 0; e < NP; ++e) b[e] = 0;
-  for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
+    for (int e = 0; e < NP; ++e) b[e] = 0;
+    for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
 #pragma unroll
-    for (int e = 0; e < NP; ++e)
-      if (b[e] + s <= nt && pre[b[e] + s] <= target[e]) b[e] += s;
-  }
-  // beyond the last tile (target at the total): the last tile's last entry
-  T lt[NP];
+      for (int e = 0; e < NP; ++e)
+        if (b[e] + s <= nt && pre[b[e] + s] <= target[e]) b[e] += s;
+    }
+    // beyond the last tile (target at the total): the last tile's last entry
+    T lt[NP];
 #pragma unroll
-  for (int e = 0; e < NP; ++e) {
-    const bool past = b[e] >= nt;
-    b[e] = past ? nt - 1u : b[e];
-    lt[e] = past ? (T)INFINITY : (T)((target[e] - pre[b[e]]) / a.gscale[b[e]]);
-  }
-  uint64_t aidx[NP];
-  tile_positions<T, NP>(gcc, a.gcoarse, a.gcdf, b, lt, lg_e, aidx);
-  // gather, propagate, store (one pair at a time)
+    for (int e = 0; e < NP; ++e) {
+      const bool past = b[e] >= nt;
+      b[e] = past ? nt - 1u : b[e];
+      lt[e] = past ? (T)INFINITY : (T)((target[e] - pre[b[e]]) / a.gscale[b[e]]);
+    }
+    uint64_t aidx[NP];
+    tile_positions<T, NP>(gcc, a.gcoarse, a.gcdf, b, lt, lg_e, aidx);
+    // gather, propagate, store (one pair at a time)
 #pragma unroll
-  for (int it = 0; it < PPT; ++it) {
-    const uint64_t p = ((uint64_t)blockIdx.x * PPT + it) * NT + threadIdx.x;
-    if (p >= npairs) continue;
-    T z[2][D], xo[2][D];
+    for (int it = 0; it < PPT; ++it) {
+      const uint64_t p = ((uint64_t)chunk * PPT + it) * NT + threadIdx.x;
+      if (p >= npairs) continue;
+      T z[2][D], xo[2][D];
 #pragma unroll
-    for (int jj = 0; jj < D; ++jj) z[0][jj] = z[1][jj] = 0;
-    z[0][0] = z0[2 * it];
-    z[1][0] = z0[2 * it + 1];
-    pair_normals_rest<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
+      for (int jj = 0; jj < D; ++jj) z[0][jj] = z[1][jj] = 0;
+      z[0][0] = z0[2 * it];
+      z[1][0] = z0[2 * it + 1];
+      pair_normals_rest<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
 #pragma unroll
-    for (int e = 0; e < 2; ++e) {
-      T xh[D];
+      for (int e = 0; e < 2; ++e) {
+        T xh[D];
+#pragma unroll
+        for (int jj = 0; jj < D; ++jj)
+          xh[jj] = (jj < d) ? Single<S, T>::load(a.x_in + (size_t)jj * N + aidx[2 * it + e]) : (T)0;
+        Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
+      }
 #pragma unroll
       for (int jj = 0; jj < D; ++jj)
-        xh[jj] = (jj < d) ? Single<S, T>::load(a.x_in + (size_t)jj * N + aidx[2 * it + e]) : (T)0;
-      Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
-    }
-#pragma unroll
-    for (int jj = 0; jj < D; ++jj)
-      if (jj < d) Pair<S, T>::store(a.x_out + (size_t)jj * N + 2 * p, xo[0][jj], xo[1][jj]);
-    if (a.anc) {
-      a.anc[2 * p] = (uint32_t)aidx[2 * it];
-      a.anc[2 * p + 1] = (uint32_t)aidx[2 * it + 1];
+        if (jj < d) Pair<S, T>::store(a.x_out + (size_t)jj * N + 2 * p, xo[0][jj], xo[1][jj]);
+      if (a.anc) {
+        a.anc[2 * p] = (uint32_t)aidx[2 * it];
+        a.anc[2 * p + 1] = (uint32_t)aidx[2 * it + 1];
+      }
     }
   }
 }

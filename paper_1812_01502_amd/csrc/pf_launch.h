@@ -41,6 +41,7 @@ struct LaunchReq {
   uint32_t grid;
   size_t lds;    // dynamic LDS bytes
   uint32_t tile_elems;  // global draw: particles per weight tile
+  uint32_t nchunks;     // global draw: chunks of pairs the (persistent) grid works through
   // finalize (LW_FINALIZE): the step whose partials are reduced
   FinArgs fin;
   const void* fin_part;
@@ -62,6 +63,8 @@ constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 :
 // Pairs per thread of the global weight kernel (256 threads).
 constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
 constexpr int kDrawPPT = 2;
+// Blocks of the persistent global draw: four per compute unit of MI355X.
+constexpr uint32_t kDrawBlocks = 1024;
 
 template <typename K> static hipError_t ensure_lds(K* kernel, size_t bytes) {
   if (bytes <= 65536) return hipSuccess;
@@ -231,7 +234,7 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       auto k = pf_global_draw<D, MK, T, S, 256, kDrawPPT>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a, rq.tile_elems);
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a, rq.tile_elems, rq.nchunks);
       return hipGetLastError();
     }
   }

@@ -519,7 +519,8 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.nt = 256;
     rq.ppt = kDrawPPT;
     const uint64_t pairs_per_block = 256ull * kDrawPPT;
-    rq.grid = (uint32_t)((h->N / 2 + pairs_per_block - 1) / pairs_per_block);
+    rq.nchunks = (uint32_t)((h->N / 2 + pairs_per_block - 1) / pairs_per_block);
+    rq.grid = std::min<uint32_t>(rq.nchunks, kDrawBlocks);
     rq.lds = h->g_ntiles <= 4096 ? (size_t)(h->g_ntiles + 1) * 8 : 16;
     rq.tile_elems = h->g_tile;
     e = launch(h, rq, &a);
