@@ -392,6 +392,41 @@ const char* pf_batch_last_error(const pf_batch* b);
 pf_status pf_set_allocator(void* (*alloc)(size_t bytes, void* ctx), void (*free_)(void* ptr, void* ctx),
                            void* ctx);
 
+/* pf_run without any device allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid hipMalloc). It runs what pf_create followed by pf_run and
+ * pf_history computes, for the butterfly path with rotating stages only
+ * (radix < N; no full_cycle, island, ess_threshold or keep_ancestors;
+ * cfg->history is ignored), on state buffers the caller owns:
+ *   x_dev     (device, in/out) d planes of N values in the storage type,
+ *             plane j = component j of every particle (as pf_get_state);
+ *   logw_dev  (device, in/out) N log-weights (float; double for F64
+ *             states), any common offset (all zero for a fresh cloud);
+ *   y_dev     (device) observation j at y_dev + j * y_stride, in the
+ *             compute type (float; double for F64), y_stride >= d;
+ *   est_dev   (device, out) n_steps records, record j for step t0 + j; the
+ *             log-normaliser accumulates from 0 at the first step of the
+ *             call.
+ * Step t0 + j uses stage (t0 + j) mod S and the random numbers of that
+ * step, so from the cloud pf_create initialises (pf_get_state at t = 0)
+ * and t0 = 0 it computes the same states, log-weights and records as
+ * pf_create + pf_run of the same configuration, bit for bit. The steps
+ * update x_dev and logw_dev in place. Every other buffer (control block,
+ * model parameters, the per-tile reduction records of one step) lives in one
+ * static device array of 1 MiB per device (kept until the process ends);
+ * its address is looked up once per device. Calls that overlap on one device
+ * (other streams or threads) share that array and race: serialise them.
+ * Asynchronous on hip_stream; calls no allocation routine (device memory
+ * comes only from the caller and the static array; the model parameters
+ * reach the device as kernel arguments). Errors, with the message in
+ * pf_last_error(NULL): PF_E_INVALID (arguments as pf_create, NULL buffers,
+ * y_stride < d), PF_E_UNSUPPORTED (a configuration outside the above, or N
+ * and d whose reduction records exceed the static array: e.g. above about
+ * 2^25 particles at d = 1, 2^22 at d = 8), PF_E_HIP. */
+pf_status pf_run_noalloc(const pf_model* model, const pf_config* cfg, void* x_dev, void* logw_dev,
+                         const void* y_dev, uint32_t n_steps, uint64_t y_stride, uint32_t t0,
+                         pf_estimate_t* est_dev, void* hip_stream);
+
 /* Static description of a status code. */
 const char* pf_status_string(pf_status s);
 

@@ -28,7 +28,7 @@ EXPORTS = ("pf_create", "pf_destroy", "pf_reset", "pf_step", "pf_run", "pf_estim
            "pf_batch_create", "pf_batch_destroy", "pf_batch_step", "pf_batch_run",
            "pf_batch_estimates", "pf_batch_filter_info", "pf_batch_tuning", "pf_batch_get_state",
            "pf_batch_set_state", "pf_batch_reset", "pf_batch_sync", "pf_batch_last_error",
-           "pf_set_allocator", "pf_batch_estimates_async", "pf_batch_rebind")
+           "pf_set_allocator", "pf_batch_estimates_async", "pf_batch_rebind", "pf_run_noalloc")
 
 DPTR = POINTER(c_double)
 # pf_set_allocator callbacks: alloc(bytes, ctx) -> device pointer, free_(ptr, ctx)
@@ -116,6 +116,8 @@ def load():
         "pf_batch_estimates_async": (c_int32, [H, c_void_p]),
         "pf_batch_rebind": (c_int32, [H, c_uint32, POINTER(c_uint32), POINTER(PfModel), POINTER(PfConfig)]),
         "pf_set_allocator": (c_int32, [ALLOC_FN, FREE_FN, c_void_p]),
+        "pf_run_noalloc": (c_int32, [POINTER(PfModel), POINTER(PfConfig), c_void_p, c_void_p, c_void_p, c_uint32,
+                                     c_uint64, c_uint32, c_void_p, c_void_p]),
         "pf_status_string": (c_char_p, [c_int32]),
         "pf_last_error": (c_char_p, [H]),
     }
