@@ -193,7 +193,7 @@ def serving_requests(rate: float, window_s: float, seed: int = 5):
     return models, reqs
 
 
-def serving_bench(window_s: float = 5.0, rates=(250.0, 500.0, 700.0, 1000.0, 2000.0), seed: int = 5):
+def serving_bench(window_s: float = 5.0, rates=(250.0, 350.0, 500.0, 700.0, 1000.0, 2000.0), seed: int = 5):
     """The serving workload at several offered loads: continuous batching
     over re-bindable slots (admission by device footprint against a 24 GiB
     budget), per-observation latency from the observation's availability to

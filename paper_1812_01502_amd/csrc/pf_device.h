@@ -75,13 +75,21 @@ template <typename T> struct Pair<bf16, T> {
 template <typename S, typename T> struct Single;
 template <typename T> struct Single<float, T> {
   static __device__ __forceinline__ T load(const float* p) { return (T)*p; }
+  static __device__ __forceinline__ float cvt(T v) { return (float)v; }
 };
 template <typename T> struct Single<double, T> {
   static __device__ __forceinline__ T load(const double* p) { return (T)*p; }
+  static __device__ __forceinline__ double cvt(T v) { return (double)v; }
 };
 template <typename T> struct Single<bf16, T> {
   static __device__ __forceinline__ T load(const bf16* p) {
     return (T)bf16_bits_to_f32(*reinterpret_cast<const uint16_t*>(p));
+  }
+  static __device__ __forceinline__ bf16 cvt(T v) {
+    const uint16_t b = (uint16_t)f32_to_bf16_bits((float)v);
+    bf16 r;
+    __builtin_memcpy(&r, &b, 2);
+    return r;
   }
 };
 

@@ -104,10 +104,11 @@ template <typename T, typename S> struct StepArgs {
   T* ess_out;
   const AdStage* stab;
   // global path scratch
-  T* gcdf;                   // within-tile inclusive CDF (N)
-  T* gcoarse;                // every 64th CDF value (N / 64)
+  T* gcdf;                   // within-tile inclusive CDF (N), for d = 1 paired with the states
+  T* gcoarse;                // coarse CDF levels (global_cc_offset)
+  S* gx;                     // d > 1: the states particle-major ([N][D]) for the draw's gather
   double* gpre;              // tile prefix, ntiles + 1 entries
-  double* gscale;            // e^{m_b - M}, ntiles entries
+  double* gscale;            // e^{m_b - M}, ntiles entries (the draw reads 1 / e^{m_b - M})
 };
 
 // ---------------------------------------------------------------------------
@@ -1542,10 +1543,27 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
 #pragma unroll
   for (int e = 0; e < NLOC; ++e) {
     c += w[e];
-    a.gcdf[base + e] = c;
+    const uint64_t i = base + e;
+    if constexpr (D == 1) {
+      // runs of 16: the CDF values, then the 16 states, so that the draw's
+      // gather reads the cache line its search has just read
+      const uint64_t r0 = 2u * (i & ~(uint64_t)15u) + (i & 15u);
+      a.gcdf[r0] = c;
+      a.gcdf[r0 + 16u] = xr[e][0];
+    } else {
+      a.gcdf[i] = c;
+    }
     const uint32_t q = (uint32_t)(tid * NLOC + e);  // position in the tile
-    if ((q & 15u) == 15u) a.gcoarse[(base + e) >> 4] = c;
+    if ((q & 15u) == 15u) a.gcoarse[i >> 4] = c;
     if ((q & 255u) == 255u) gcc[(size_t)tile * 16u + (q >> 8)] = c;
+  }
+  if constexpr (D > 1) {
+    // the states particle-major: one contiguous row per particle to gather
+#pragma unroll
+    for (int e = 0; e < NLOC; ++e) {
+#pragma unroll
+      for (int j = 0; j < D; ++j) a.gx[(base + e) * D + j] = Single<S, T>::cvt(j < d ? xr[e][j] : (T)0);
+    }
   }
   T* prt = a.part_out + (size_t)tile * PS;
   tile_partials<D, T, NT, NLOC>(lr, xr, lwn, sh, d, mtile, red, prt);
@@ -1625,6 +1643,9 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
       if (c + k < b1) {
         a.gpre[c + k] = run;
         run += ev[k] * (double)sv[k];
+        // the draw scales by the reciprocal (a tile whose scale underflows
+        // to 0 has no weight and is never drawn)
+        a.gscale[c + k] = 1.0 / ev[k];
       }
     }
   }
@@ -1650,17 +1671,50 @@ __device__ __forceinline__ uint32_t count_le16(const T* run, T v, uint32_t n) {
   T x[16];
 #pragma unroll
   for (int k = 0; k < 16; ++k) x[k] = q[k];
-  uint32_t c = 0;
+  // entries past n never count
 #pragma unroll
-  for (int k = 0; k < 16; ++k) c += ((uint32_t)k < n && x[k] <= v) ? 1u : 0u;
+  for (int k = 1; k < 16; ++k) x[k] = (uint32_t)k < n ? x[k] : (T)INFINITY;
+  // the run does not decrease, so the count is a binary search on the
+  // registers: each level keeps the half that holds the boundary
+  uint32_t c = 0;
+  bool h = x[7] <= v;
+  c += h ? 8u : 0u;
+  T y[8];
+#pragma unroll
+  for (int k = 0; k < 8; ++k) y[k] = h ? x[k + 8] : x[k];
+  h = y[3] <= v;
+  c += h ? 4u : 0u;
+  T z[4];
+#pragma unroll
+  for (int k = 0; k < 4; ++k) z[k] = h ? y[k + 4] : y[k];
+  h = z[1] <= v;
+  c += h ? 2u : 0u;
+  const T w0 = h ? z[2] : z[0], w1 = h ? z[3] : z[1];
+  c += (w0 <= v ? 1u : 0u) + (w0 <= v && w1 <= v ? 1u : 0u);
   return c;
+}
+
+// Number of tile prefixes pre[1..nt] that are <= target[e], for NP draws
+// together (binary search).
+template <int NP>
+__device__ __forceinline__ void tile_search(const double* pre, uint32_t nt, const double (&target)[NP],
+                                            uint32_t (&b)[NP]) {
+#pragma unroll
+  for (int e = 0; e < NP; ++e) b[e] = 0;
+  for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
+#pragma unroll
+    for (int e = 0; e < NP; ++e)
+      if (b[e] + s <= nt && pre[b[e] + s] <= target[e]) b[e] += s;
+  }
 }
 
 // Particle index of the first CDF entry above lt[e] in weight tile b[e] (at
 // most the tile's last), for NP draws level by level: the every-256th level
 // (16 slots per tile, ncc = E / 256 of them used), the every-16th level, the
 // CDF itself. E = 2^lg_e >= 128 particles per tile.
-template <typename T, int NP>
+// PAIRED: the CDF is stored in runs of 16 followed by 16 other values (the
+// states, for d = 1), so run j of a tile starts at twice its particle index.
+template <typename T, int NP, bool PAIRED>
 __device__ __forceinline__ void tile_positions(const T* gcc, const T* gcoarse, const T* gcdf, const uint32_t (&b)[NP],
                                                const T (&lt)[NP], uint32_t lg_e, uint64_t (&aidx)[NP]) {
   const uint32_t nb = 1u << (lg_e - 4u);        // 16-entry runs per tile
@@ -1684,7 +1738,7 @@ __device__ __forceinline__ void tile_positions(const T* gcc, const T* gcoarse, c
 #pragma unroll
   for (int e = 0; e < NP; ++e) {
     const uint64_t run0 = ((uint64_t)b[e] << lg_e) + 16u * j[e];
-    const uint32_t c = count_le16<T, 16 * sizeof(T)>(gcdf + run0, lt[e], 16u);
+    const uint32_t c = count_le16<T, 16 * sizeof(T)>(gcdf + (PAIRED ? 2u * run0 : run0), lt[e], 16u);
     aidx[e] = run0 + (c < 16u ? c : 15u);
   }
 }
@@ -1728,25 +1782,21 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
       const uint64_t i = 2ull * pr[e >> 1] + (uint64_t)(e & 1);
       target[e] = a.systematic ? ((double)i + u0sys) * total / (double)N : (double)u[e] * total;
     }
-    // tile: number of tile prefixes P_1..P_nt that are <= target
+    // tile: number of tile prefixes P_1..P_nt that are <= target (the LDS
+    // copy through a pointer the compiler knows is LDS)
     uint32_t b[NP];
-#pragma unroll
-    for (int e = 0; e < NP; ++e) b[e] = 0;
-    for (uint32_t s = 1u << (31u - __clz(nt)); s >= 1u; s >>= 1) {
-#pragma unroll
-      for (int e = 0; e < NP; ++e)
-        if (b[e] + s <= nt && pre[b[e] + s] <= target[e]) b[e] += s;
-    }
+    if (pre_in_lds) tile_search<NP>(spre, nt, target, b);
+    else tile_search<NP>(a.gpre, nt, target, b);
     // beyond the last tile (target at the total): the last tile's last entry
     T lt[NP];
 #pragma unroll
     for (int e = 0; e < NP; ++e) {
       const bool past = b[e] >= nt;
       b[e] = past ? nt - 1u : b[e];
-      lt[e] = past ? (T)INFINITY : (T)((target[e] - pre[b[e]]) / a.gscale[b[e]]);
+      lt[e] = past ? (T)INFINITY : (T)((target[e] - pre[b[e]]) * a.gscale[b[e]]);
     }
     uint64_t aidx[NP];
-    tile_positions<T, NP>(gcc, a.gcoarse, a.gcdf, b, lt, lg_e, aidx);
+    tile_positions<T, NP, D == 1>(gcc, a.gcoarse, a.gcdf, b, lt, lg_e, aidx);
     // gather, propagate, store (one pair at a time)
 #pragma unroll
     for (int it = 0; it < PPT; ++it) {
@@ -1760,10 +1810,14 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
       pair_normals_rest<D, T>((uint32_t)p, tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
 #pragma unroll
       for (int e = 0; e < 2; ++e) {
+        const uint64_t ai = aidx[2 * it + e];
         T xh[D];
+        if constexpr (D == 1) {
+          xh[0] = a.gcdf[2u * (ai & ~(uint64_t)15u) + 16u + (ai & 15u)];
+        } else {
 #pragma unroll
-        for (int jj = 0; jj < D; ++jj)
-          xh[jj] = (jj < d) ? Single<S, T>::load(a.x_in + (size_t)jj * N + aidx[2 * it + e]) : (T)0;
+          for (int jj = 0; jj < D; ++jj) xh[jj] = Single<S, T>::load(a.gx + ai * D + jj);
+        }
         Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
       }
 #pragma unroll

@@ -66,6 +66,7 @@ struct pf_handle {
   uint32_t* anc = nullptr;
   void* gcdf = nullptr;
   void* gcoarse = nullptr;
+  void* gx = nullptr;
   double* gpre = nullptr;
   double* gscale = nullptr;
   uint32_t g_tile = 0, g_ntiles = 0, g_nt = 256, g_ppt = 1;
@@ -172,6 +173,7 @@ template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>&
   a.systematic = h->resampler == PF_RESAMPLE_SYSTEMATIC ? 1 : 0;
   a.gcdf = reinterpret_cast<T*>(h->gcdf);
   a.gcoarse = reinterpret_cast<T*>(h->gcoarse);
+  a.gx = reinterpret_cast<S*>(h->gx);
   a.gpre = h->gpre;
   a.gscale = h->gscale;
 }
@@ -1000,7 +1002,10 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
     h->isl_lv = p;
   }
   if (h->global) {
-    if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz)) != PF_OK) return bail(s);
+    // d = 1: the CDF in runs of 16 paired with the states (2 N values);
+    // d > 1: the CDF (N) and the states particle-major (N D storage values)
+    if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz * (h->D == 1 ? 2 : 1))) != PF_OK) return bail(s);
+    if (h->D > 1 && (s = dalloc(h, &h->gx, (size_t)N * h->D * h->ssz)) != PF_OK) return bail(s);
     if ((s = dalloc(h, &h->gcoarse, (size_t)global_coarse_elems(N, h->g_ntiles) * h->tsz)) != PF_OK)
       return bail(s);
     if ((s = dalloc(h, &p, (size_t)(h->g_ntiles + 1) * 8)) != PF_OK) return bail(s);

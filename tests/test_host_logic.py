@@ -234,7 +234,8 @@ def test_global_draw_tile_positions():
     coarse levels hold every 16th and every 256th entry of the tile CDF in the
     device layout (global_cc_offset), it returns what a plain binary search
     of the tile CDF returns (the number of entries <= target, at most E - 1)
-    for every tile size the runtime uses (E = 128 .. 4096), with zero weights,
+    for every tile size the runtime uses (E = 128 .. 4096), with the CDF
+    contiguous or in runs of 16 paired with 16 other values, with zero weights,
     ties, targets equal to an entry, below the first and above the last; no
     read leaves the arrays as the runtime sizes them."""
     import os
@@ -251,17 +252,18 @@ def test_global_draw_tile_positions():
              re.search(r"__host__ __device__ constexpr uint64_t global_coarse_elems\(.*?\n}\n", ker, re.S).group(0),
              re.search(r"template <typename T, int ALIGN>\n__device__ __forceinline__ uint32_t count_le16\(.*?\n}\n",
                        ker, re.S).group(0),
-             re.search(r"template <typename T, int NP>\n__device__ __forceinline__ void tile_positions\(.*?\n}\n",
-                       ker, re.S).group(0)]
+             re.search(r"template <typename T, int NP, bool PAIRED>\n__device__ __forceinline__ void tile_positions\("
+                       r".*?\n}\n", ker, re.S).group(0)]
     src = ("#define __device__\n#define __host__\n#define __forceinline__ inline\n"
            "#include <cstdint>\n#include <cstddef>\n#include <cstdio>\n#include <random>\n#include <vector>\n"
            "#include <cmath>\n" + "\n".join(parts) + r'''
+template <bool PAIRED>
 long check(uint32_t lg_e, uint32_t nt, std::mt19937& g, long& cases) {
   const uint32_t E = 1u << lg_e;
   const uint64_t N = (uint64_t)E * nt;
   long bad = 0;
   for (int trial = 0; trial < 40; ++trial) {
-    std::vector<float> cdf(N), coarse(global_coarse_elems(N, nt));
+    std::vector<float> cdf(N), coarse(global_coarse_elems(N, nt)), dev(PAIRED ? 2 * N : N);
     float* cc = coarse.data() + global_cc_offset(N);
     for (uint32_t b = 0; b < nt; ++b) {
       float acc = 0.f;
@@ -270,6 +272,8 @@ long check(uint32_t lg_e, uint32_t nt, std::mt19937& g, long& cases) {
         acc += kind < 2 ? 0.f : (kind == 2 ? 1.f : (float)(g() % 1000u) * 1e-3f);
         const uint64_t i = (uint64_t)b * E + q;
         cdf[i] = acc;
+        dev[PAIRED ? 2 * (i & ~(uint64_t)15) + (i & 15) : i] = acc;
+        if (PAIRED) dev[2 * (i & ~(uint64_t)15) + 16 + (i & 15)] = -7.f;   // the paired states
         if ((q & 15u) == 15u) coarse[i >> 4] = acc;
         if ((q & 255u) == 255u) cc[(size_t)b * 16u + (q >> 8)] = acc;
       }
@@ -290,7 +294,7 @@ long check(uint32_t lg_e, uint32_t nt, std::mt19937& g, long& cases) {
           if (t[pos + s - 1u] <= lt[e]) pos += s;
         want[e] = (uint64_t)bb[e] * E + pos;
       }
-      tile_positions<float, NP>(cc, coarse.data(), cdf.data(), bb, lt, lg_e, got);
+      tile_positions<float, NP, PAIRED>(cc, coarse.data(), dev.data(), bb, lt, lg_e, got);
       for (int e = 0; e < NP; ++e) {
         ++cases;
         if (got[e] != want[e]) ++bad;
@@ -303,7 +307,7 @@ int main() {
   std::mt19937 g(11);
   long cases = 0, bad = 0;
   for (uint32_t lg_e : {7u, 9u, 10u, 11u, 12u})
-    for (uint32_t nt : {1u, 3u}) bad += check(lg_e, nt, g, cases);
+    for (uint32_t nt : {1u, 3u}) bad += check<false>(lg_e, nt, g, cases) + check<true>(lg_e, nt, g, cases);
   printf("%ld %ld\n", cases, bad);
   return 0;
 }
@@ -317,4 +321,4 @@ int main() {
     finally:
         shutil.rmtree(d, ignore_errors=True)
     cases, bad = int(out[0]), int(out[1])
-    assert cases == 5 * 2 * 40 * 64 * 4 and bad == 0, (cases, bad)
+    assert cases == 2 * 5 * 2 * 40 * 64 * 4 and bad == 0, (cases, bad)
