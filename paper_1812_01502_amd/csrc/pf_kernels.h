@@ -109,6 +109,11 @@ template <typename T, typename S> struct StepArgs {
   S* gx;                     // d > 1: the states particle-major ([N][D]) for the draw's gather
   double* gpre;              // tile prefix, ntiles + 1 entries
   double* gscale;            // e^{m_b - M}, ntiles entries (the draw reads 1 / e^{m_b - M})
+  // systematic global draw (nullable otherwise): the first output drawn from
+  // each weight tile (ntiles + 1 entries, the last N) and the work items
+  // ([0] = count, then (tile, first output) pairs from word 2)
+  uint32_t* gfirst;
+  uint32_t* gwork;
 };
 
 // ---------------------------------------------------------------------------
@@ -1476,6 +1481,101 @@ __host__ __device__ constexpr uint64_t global_coarse_elems(uint64_t N, uint64_t 
   return global_cc_offset(N) + 16u * ntiles;
 }
 
+// Sixteen bytes as native vectors (kept in registers when held in arrays).
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ void store16(float* p, const float* v) {
+  *reinterpret_cast<f32x4*>(p) = f32x4{v[0], v[1], v[2], v[3]};
+}
+__device__ __forceinline__ void store16(double* p, const double* v) {
+  *reinterpret_cast<f64x2*>(p) = f64x2{v[0], v[1]};
+}
+
+// Systematic global resampling: output i (0 <= i < N) draws the target
+// (i + U) total / N, with U the step's single uniform. N is a power of two,
+// so the scale total / N is exact and the target equals ((i + U) total) / N.
+// The targets do not decrease with i, so the outputs of each weight tile form
+// one contiguous range; the draw works through them in items of at most
+// kSysItem outputs.
+constexpr uint32_t kSysItem = 8192;
+__host__ __device__ constexpr uint64_t sys_max_items(uint64_t N, uint64_t ntiles) {
+  return ntiles + N / kSysItem + 1u;
+}
+__device__ __forceinline__ double sys_target(uint32_t i, double u0, double scale) {
+  return ((double)i + u0) * scale;
+}
+// Smallest i in [0, N] whose target reaches p (N when none below N does):
+// a guess from the inverse of the target, checked, then halving.
+__device__ inline uint64_t sys_first_output(double p, double u0, double scale, uint64_t N) {
+  auto reaches = [&](uint64_t i) { return i >= N || sys_target((uint32_t)i, u0, scale) >= p; };
+  uint64_t lo = 0, hi = N;  // the answer lies in [lo, hi]
+  const double x = scale > 0.0 ? p / scale - u0 : 0.0;
+  if (x > 2.0 && x < (double)N - 3.0) {  // false for a NaN
+    const uint64_t g = (uint64_t)x;
+    if (!reaches(g - 2u)) lo = g - 1u;
+    if (reaches(g + 2u)) hi = g + 2u;
+  }
+  while (lo < hi) {
+    const uint64_t mid = lo + ((hi - lo) >> 1);
+    if (reaches(mid)) {
+      hi = mid;
+    } else {
+      lo = mid + 1u;
+    }
+  }
+  return lo;
+}
+
+// In-tile value of output start + j of weight tile b: the target less the
+// tile's prefix, in the tile's CDF units (the largest value at or past the
+// total, the targets that fall beyond the last tile).
+template <typename T>
+__device__ __forceinline__ T sys_value(uint32_t i, double u0, double scale, double total, double preb,
+                                       double scb) {
+  const double tg = sys_target(i, u0, scale);
+  return tg >= total ? (T)INFINITY : (T)((tg - preb) * scb);
+}
+// Number of an item's outputs start + j (0 <= j < n) whose in-tile value is
+// below v: the values do not decrease with j, so this is the first j whose
+// value reaches v (n when none does). The guess is the ceiling of the inverse
+// of the target (ev = 1 / scb, inv_scale = 1 / scale, base = U + start);
+// two checks confirm it in the common case, else a bracket and halving.
+template <typename T>
+__device__ inline uint32_t sys_outputs_below(T v, uint32_t n, uint32_t start, double u0, double base,
+                                             double scale, double inv_scale, double total, double preb,
+                                             double scb, double ev) {
+  auto reaches = [&](uint32_t j) { return j >= n || sys_value<T>(start + j, u0, scale, total, preb, scb) >= v; };
+  const double x = ((double)v * ev + preb) * inv_scale - base;
+  uint32_t g;
+  if (!(x > 0.0)) {
+    g = 0u;  // also a NaN
+  } else if (x >= (double)n) {
+    g = n;
+  } else {
+    g = (uint32_t)ceil(x);
+  }
+  if (reaches(g) && (g == 0u || !reaches(g - 1u))) return g;
+  // the answer lies in [lo, hi]
+  uint32_t lo = g > 1u ? g - 1u : 0u, hi = g + 1u < n ? g + 1u : n;
+  if (lo > 0u && reaches(lo - 1u)) {
+    hi = lo - 1u;
+    lo = 0u;
+  } else if (!reaches(hi)) {
+    lo = hi + 1u;
+    hi = n;
+  }
+  while (lo < hi) {
+    const uint32_t mid = lo + ((hi - lo) >> 1);
+    if (reaches(mid)) {
+      hi = mid;
+    } else {
+      lo = mid + 1u;
+    }
+  }
+  return lo;
+}
+
 template <int D, int MK, typename T, typename S, int NT, int PPT>
 __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   constexpr int NLOC = 2 * PPT;
@@ -1483,6 +1583,7 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   constexpr uint32_t E = 2u * NT * PPT;
   __shared__ T red[(NT / 64) * PS];
   __shared__ T wtot[NT / 64];
+  __shared__ T wmx[NT / 64];
   __shared__ T shx[D];
   const int d = (int)a.d;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
@@ -1538,12 +1639,39 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     if (i == wv) woff = tot;
     tot += wtot[i];
   }
-  T c = woff + incl - run;
+  // the thread's CDF values; each is then raised to the largest value of
+  // the threads before it, so that the tile's CDF never decreases (the
+  // per-thread offsets and the running sums round differently)
+  T cv[NLOC];
+  {
+    T c = woff + incl - run;
+#pragma unroll
+    for (int e = 0; e < NLOC; ++e) {
+      c += w[e];
+      cv[e] = c;
+    }
+    T lm = c;  // inclusive max over the wave's lanes
+#pragma unroll
+    for (int s = 1; s < 64; s <<= 1) {
+      const T o = __shfl_up(lm, (unsigned)s, 64);
+      if (lane >= s) lm = fmaxT(lm, o);
+    }
+    if (lane == 63) wmx[wv] = lm;
+    T before = __shfl_up(lm, 1u, 64);
+    if (lane == 0) before = 0;  // the CDF is not negative
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NT / 64; ++i)
+      if (i < wv) before = fmaxT(before, wmx[i]);
+#pragma unroll
+    for (int e = 0; e < NLOC; ++e) cv[e] = fmaxT(cv[e], before);
+  }
   T* gcc = a.gcoarse + global_cc_offset(N);  // every 256th entry, 16 slots per tile
 #pragma unroll
   for (int e = 0; e < NLOC; ++e) {
-    c += w[e];
+    const T c = cv[e];
     const uint64_t i = base + e;
+    if (a.systematic) continue;  // below: the plain CDF
     if constexpr (D == 1) {
       // runs of 16: the CDF values, then the 16 states, so that the draw's
       // gather reads the cache line its search has just read
@@ -1553,11 +1681,23 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
     } else {
       a.gcdf[i] = c;
     }
+    // the coarse levels serve the multinomial draw's search
     const uint32_t q = (uint32_t)(tid * NLOC + e);  // position in the tile
     if ((q & 15u) == 15u) a.gcoarse[i >> 4] = c;
     if ((q & 255u) == 255u) gcc[(size_t)tile * 16u + (q >> 8)] = c;
   }
-  if constexpr (D > 1) {
+  if (a.systematic) {
+    // the systematic draw reads the plain CDF, and the states where they are
+    constexpr int VE = (int)(16u / sizeof(T));
+    if constexpr (NLOC % VE == 0) {
+#pragma unroll
+      for (int e = 0; e < NLOC; e += VE) store16(a.gcdf + base + e, cv + e);
+    } else {
+#pragma unroll
+      for (int e = 0; e < NLOC; ++e) a.gcdf[base + e] = cv[e];
+    }
+  }
+  if (D > 1 && !a.systematic) {
     // the states particle-major: one contiguous row per particle to gather
 #pragma unroll
     for (int e = 0; e < NLOC; ++e) {
@@ -1579,7 +1719,7 @@ template <int D, typename T, typename S, int NT>
 __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   __shared__ double sd[NT];
   constexpr int PS = partial_stride(D);
-  constexpr uint32_t CH = 16;
+  constexpr uint32_t CH = NT >= 1024 ? 4 : 16;
   const T* part = a.part_out;
   const uint32_t nt = a.ntiles;
   const int tid = threadIdx.x;
@@ -1629,6 +1769,12 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     __syncthreads();
   }
   double run = sd[tid] - loc;
+  // systematic: the first output of each tile, from its prefix
+  const bool plan = a.systematic && a.gwork != nullptr;
+  const uint64_t N = a.N;
+  const double scale = sd[NT - 1] / (double)N;
+  const double u0 = plan ? word_uniform<double>(philox(0u, a.t + 1u, 0u, a.sid, a.k0, a.k1).w0) : 0.0;
+  uint32_t ofirst = 0, omax = 0, cnt = 0;
   for (uint32_t c = b0; c < b1; c += CH) {
     T sv[CH];
     double ev[CH];
@@ -1642,6 +1788,18 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     for (uint32_t k = 0; k < CH; ++k) {
       if (c + k < b1) {
         a.gpre[c + k] = run;
+        if (plan) {
+          // non-decreasing within the thread; the items of the tile before
+          const uint32_t o = (uint32_t)sys_first_output(run, u0, scale, N);
+          const uint32_t om = o > omax ? o : omax;
+          if (c + k == b0) {
+            ofirst = om;
+          } else {
+            cnt += (om - omax + kSysItem - 1u) / kSysItem;
+          }
+          omax = om;
+          a.gfirst[c + k] = om;
+        }
         run += ev[k] * (double)sv[k];
         // the draw scales by the reciprocal (a tile whose scale underflows
         // to 0 has no weight and is never drawn)
@@ -1650,6 +1808,72 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     }
   }
   if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
+  if (plan) {
+    // the tiles' ranges split [0, N) exactly: the first outputs are made
+    // non-decreasing over the block (the last tile also takes any target at
+    // the total); then each tile's items of at most kSysItem outputs
+    __shared__ uint32_t su[NT];
+    __shared__ uint32_t sfirst[NT + 1];
+    const bool has = b0 < b1;
+    su[tid] = omax;
+    __syncthreads();
+    for (int s = 1; s < NT; s <<= 1) {
+      const uint32_t o = tid >= s ? su[tid - s] : 0u;
+      __syncthreads();
+      su[tid] = o > su[tid] ? o : su[tid];
+      __syncthreads();
+    }
+    const uint32_t before = tid > 0 ? su[tid - 1] : 0u;
+    sfirst[tid] = has ? (ofirst > before ? ofirst : before) : (uint32_t)N;
+    if (tid == 0) sfirst[NT] = (uint32_t)N;
+    if (tid == 0) a.gfirst[nt] = (uint32_t)N;
+    __syncthreads();
+    const uint32_t next = sfirst[tid + 1];
+    if (has) {
+      if (ofirst < before) {
+        // rare (prefixes that differ in the last place across threads):
+        // raise the thread's leading entries and count again
+        cnt = 0;
+        uint32_t prev = 0;
+        for (uint32_t b = b0; b < b1; ++b) {
+          const uint32_t o = a.gfirst[b] > before ? a.gfirst[b] : before;
+          a.gfirst[b] = o;
+          if (b > b0) cnt += (o - prev + kSysItem - 1u) / kSysItem;
+          prev = o;
+        }
+      }
+      const uint32_t last = omax > before ? omax : before;
+      cnt += (next - last + kSysItem - 1u) / kSysItem;
+    }
+    __syncthreads();
+    su[tid] = cnt;
+    __syncthreads();
+    for (int s = 1; s < NT; s <<= 1) {
+      const uint32_t o = tid >= s ? su[tid - s] : 0u;
+      __syncthreads();
+      su[tid] += o;
+      __syncthreads();
+    }
+    uint32_t wi = su[tid] - cnt;
+    for (uint32_t c = b0; c < b1; c += CH) {
+      uint32_t of[CH + 1];
+#pragma unroll
+      for (uint32_t k = 0; k < CH; ++k) of[k] = c + k < b1 ? a.gfirst[c + k] : next;
+      of[CH] = c + CH < b1 ? a.gfirst[c + CH] : next;
+#pragma unroll
+      for (uint32_t k = 0; k < CH; ++k) {
+        if (c + k < b1) {
+          const uint32_t e = c + k + 1u < b1 ? of[k + 1] : next;
+          for (uint32_t o = of[k]; o < e; o += kSysItem) {
+            a.gwork[2u + 2u * wi] = c + k;
+            a.gwork[3u + 2u * wi] = o;
+            ++wi;
+          }
+        }
+      }
+    }
+    if (tid == NT - 1) a.gwork[0] = su[NT - 1];
+  }
   if (tid == 0) *off_slot(a.ctl, a.u + 1, 0) = ord_encode(0.0);
   step_bookkeeping(a);
 }
@@ -1826,6 +2050,167 @@ __global__ void __launch_bounds__(NT) pf_global_draw(StepArgs<T, S> a, uint32_t 
       if (a.anc) {
         a.anc[2 * p] = (uint32_t)aidx[2 * it];
         a.anc[2 * p + 1] = (uint32_t)aidx[2 * it + 1];
+      }
+    }
+  }
+}
+
+// Global path, kernel 3 for systematic resampling, by offspring ranges
+// instead of a search per draw. A persistent grid works through the items of
+// kernel 2's plan (one weight tile, at most kSysItem consecutive outputs).
+// Per item: each particle q of the tile takes the outputs j with
+// cdf_{q-1} <= value_j < cdf_q (the last particle also every value at or
+// above its CDF), found by inverting the monotone values at cdf_q; the CDF
+// is read once, coalesced, and never decreases (kernel 1), so the ranges
+// split the item's outputs exactly. The particles write their index over
+// their range in LDS; then the pairs of outputs draw their normals, gather
+// (d = 1: the tile's states staged in LDS), propagate and store, coalesced.
+// Item w of the systematic draw: its tile, first output, end of the tile's
+// outputs, the tile's prefix and reciprocal scale, and this thread's 16-byte
+// loads of the tile's CDF (pc) and, d = 1, of its states (px). Every slot
+// loads (a slot past the tile reads the tile's first values, which are not
+// used), so that the slots stay in registers.
+template <int D, typename T, typename S, int NT, int PF, int PFX>
+__device__ __forceinline__ void sys_fetch(const StepArgs<T, S>& a, uint32_t w, uint32_t lg_e, uint32_t& b,
+                                          uint32_t& start, uint32_t& lim, double& preb, double& scb,
+                                          u32x4 (&pc)[PF], u32x4 (&px)[PFX]) {
+  constexpr uint32_t VE = 16u / sizeof(T), VS = 16u / sizeof(S);
+  b = a.gwork[2u + 2u * w];
+  start = a.gwork[3u + 2u * w];
+  lim = a.gfirst[b + 1u];
+  preb = a.gpre[b];
+  scb = a.gscale[b];
+  const uint64_t tb = (uint64_t)b << lg_e;
+  const uint32_t E = 1u << lg_e;
+  const u32x4* srcc = reinterpret_cast<const u32x4*>(a.gcdf + tb);
+#pragma unroll
+  for (int k = 0; k < PF; ++k) {
+    const uint32_t v = threadIdx.x + (uint32_t)k * NT;
+    pc[k] = srcc[v < E / VE ? v : 0u];
+  }
+  if constexpr (D == 1) {
+    const u32x4* srcx = reinterpret_cast<const u32x4*>(a.x_in + tb);
+#pragma unroll
+    for (int k = 0; k < PFX; ++k) {
+      const uint32_t v = threadIdx.x + (uint32_t)k * NT;
+      px[k] = srcx[v < E / VS ? v : 0u];
+    }
+  }
+}
+
+// Global path, kernel 3 for systematic resampling, by offspring ranges
+// instead of a search per draw. A persistent grid works through the items of
+// kernel 2's plan (one weight tile, at most kSysItem consecutive outputs).
+// Per item: each particle q of the tile takes the outputs j with
+// cdf_{q-1} <= value_j < cdf_q (the last particle also every value at or
+// above its CDF), found by inverting the monotone values at cdf_q; the CDF
+// is read once, coalesced, and never decreases (kernel 1), so the ranges
+// split the item's outputs exactly. The particles write their index over
+// their range in LDS; then the pairs of outputs draw their normals, gather
+// (d = 1: the tile's states staged in LDS; else from the state planes, whose
+// reads follow the non-decreasing ancestors), propagate and store, coalesced.
+// The next item's loads are issued before the current item's outputs.
+template <int D, int MK, typename T, typename S, int NT>
+__global__ void __launch_bounds__(NT) pf_global_sys_draw(StepArgs<T, S> a, uint32_t tile_elems) {
+  extern __shared__ __align__(16) unsigned char smem[];
+  const uint32_t E = tile_elems;  // at most 4096
+  // LDS: d = 1, the tile's states; the output count below each CDF value;
+  // the tile's CDF, whose space then holds each output's ancestor (its
+  // position in the tile)
+  S* sxs = reinterpret_cast<S*>(smem);
+  uint16_t* sf = reinterpret_cast<uint16_t*>(smem + (D == 1 ? (size_t)E * sizeof(S) : 0u));
+  T* scdf = reinterpret_cast<T*>(sf + E);
+  uint16_t* spos = reinterpret_cast<uint16_t*>(scdf);
+  const uint32_t nwork = a.gwork[0];
+  const uint32_t nt = a.ntiles;
+  const uint64_t N = a.N;
+  const double total = a.gpre[nt];
+  const double scale = total / (double)N, inv_scale = (double)N / total;
+  const uint32_t tau = a.t + 1u;
+  const double u0 = word_uniform<double>(philox(0u, tau, 0u, a.sid, a.k0, a.k1).w0);
+  const int d = (int)a.d;
+  const uint32_t lg_e = 31u - __clz(E);
+  constexpr uint32_t VE = 16u / sizeof(T), VS = 16u / sizeof(S);
+  constexpr int PF = (int)((4096u / VE + NT - 1u) / NT);
+  constexpr int PFX = D == 1 ? (int)((4096u / VS + NT - 1u) / NT) : 1;
+  uint32_t b = 0, start = 0, lim = 0;
+  double preb = 0.0, scb = 0.0;
+  u32x4 pc[PF], px[PFX];
+  if (blockIdx.x < nwork) sys_fetch<D, T, S, NT, PF, PFX>(a, blockIdx.x, lg_e, b, start, lim, preb, scb, pc, px);
+  for (uint32_t w = blockIdx.x; w < nwork; w += gridDim.x) {
+    const uint32_t end = lim - start > kSysItem ? start + kSysItem : lim;
+    const uint32_t n = end - start, s0 = start;
+    const uint64_t tbase = (uint64_t)b << lg_e;
+    const double ev = 1.0 / scb, base = u0 + (double)s0, pb = preb, sb = scb;
+    __syncthreads();  // the previous item's reads of LDS are done
+#pragma unroll
+    for (int k = 0; k < PF; ++k) {
+      const uint32_t v = threadIdx.x + (uint32_t)k * NT;
+      if (v < E / VE) *reinterpret_cast<u32x4*>(scdf + v * VE) = pc[k];
+    }
+    if constexpr (D == 1) {
+#pragma unroll
+      for (int k = 0; k < PFX; ++k) {
+        const uint32_t v = threadIdx.x + (uint32_t)k * NT;
+        if (v < E / VS) *reinterpret_cast<u32x4*>(sxs + v * VS) = px[k];
+      }
+    }
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < E; q += NT)
+      sf[q] = (uint16_t)sys_outputs_below<T>(scdf[q], n, s0, u0, base, scale, inv_scale, total, pb, sb, ev);
+    __syncthreads();
+    for (uint32_t q = threadIdx.x; q < E; q += NT) {
+      const uint32_t lo = q == 0u ? 0u : (uint32_t)sf[q - 1u];
+      const uint32_t hi = q == E - 1u ? n : (uint32_t)sf[q];
+      for (uint32_t j = lo; j < hi; ++j) spos[j] = (uint16_t)q;
+    }
+    __syncthreads();
+    if (w + gridDim.x < nwork)
+      sys_fetch<D, T, S, NT, PF, PFX>(a, w + gridDim.x, lg_e, b, start, lim, preb, scb, pc, px);
+    const uint32_t p_lo = s0 >> 1, p_end = (end + 1u) >> 1;
+    for (uint32_t p = p_lo + threadIdx.x; p < p_end; p += NT) {
+      T z[2][D], xo[2][D];
+#pragma unroll
+      for (int jj = 0; jj < D; ++jj) z[0][jj] = z[1][jj] = 0;
+      T uu0, uu1;
+      pair_block0<T>(p, tau, a.sid, a.k0, a.k1, uu0, uu1, z[0][0], z[1][0]);
+      pair_normals_rest<D, T>(p, tau, a.sid, a.k0, a.k1, d, z[0], z[1]);
+      bool in[2];
+      uint32_t q[2];
+#pragma unroll
+      for (int e = 0; e < 2; ++e) {
+        const uint32_t i = 2u * p + (uint32_t)e;
+        in[e] = i >= s0 && i < end;
+        const uint32_t qq = in[e] ? (uint32_t)spos[i - s0] : 0u;
+        q[e] = qq < E ? qq : E - 1u;
+        T xh[D];
+        if constexpr (D == 1) {
+          xh[0] = Single<S, T>::load(sxs + q[e]);
+        } else {
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj)
+            xh[jj] = jj < d ? Single<S, T>::load(a.x_in + (size_t)jj * N + tbase + q[e]) : (T)0;
+        }
+        Model<D, MK, T>::propagate(a.mp, xh, z[e], xo[e]);
+      }
+      if (in[0] && in[1]) {
+#pragma unroll
+        for (int jj = 0; jj < D; ++jj)
+          if (jj < d) Pair<S, T>::store(a.x_out + (size_t)jj * N + 2u * p, xo[0][jj], xo[1][jj]);
+        if (a.anc) {
+          a.anc[2u * p] = (uint32_t)(tbase + q[0]);
+          a.anc[2u * p + 1u] = (uint32_t)(tbase + q[1]);
+        }
+      } else {
+        // a pair split between two items: each writes its own output
+#pragma unroll
+        for (int e = 0; e < 2; ++e) {
+          if (!in[e]) continue;
+#pragma unroll
+          for (int jj = 0; jj < D; ++jj)
+            if (jj < d) a.x_out[(size_t)jj * N + 2u * p + e] = Single<S, T>::cvt(xo[e][jj]);
+          if (a.anc) a.anc[2u * p + e] = (uint32_t)(tbase + q[e]);
+        }
       }
     }
   }

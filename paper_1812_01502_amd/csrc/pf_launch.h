@@ -25,7 +25,8 @@ enum LaunchWhat : int {
   LW_AD_WEIGHT = 10,
   LW_AD_STAGE = 11,
   LW_AD_DECIDE = 12,
-  LW_AD_PROPAGATE = 13
+  LW_AD_PROPAGATE = 13,
+  LW_GLOBAL_SYS_DRAW = 14
 };
 
 // What the runtime asks for.
@@ -63,6 +64,15 @@ constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 :
 // Pairs per thread of the global weight kernel (256 threads).
 constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
 constexpr int kDrawPPT = 2;
+// Threads of the one-block global prefix kernel.
+constexpr int kPrefixNT = 1024;
+// LDS of the systematic global draw: d = 1, the tile's states; the output
+// count below each CDF value; the tile's CDF, then the item's ancestor
+// positions in the same space.
+constexpr size_t sys_draw_lds(int D, size_t tsz, size_t ssz, uint32_t tile_elems) {
+  const size_t cdf = (size_t)tile_elems * tsz, pos = (size_t)kSysItem * 2u;
+  return (D == 1 ? (size_t)tile_elems * ssz : 0u) + (size_t)tile_elems * 2u + (cdf > pos ? cdf : pos);
+}
 // Blocks of the persistent global draw: four per compute unit of MI355X.
 constexpr uint32_t kDrawBlocks = 1024;
 
@@ -166,10 +176,10 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       return hipErrorInvalidValue;
     }
     case LW_GLOBAL_PREFIX: {
-      auto k = pf_global_prefix<D, T, S, 256>;
+      auto k = pf_global_prefix<D, T, S, kPrefixNT>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, dim3(1), dim3(256), rq.lds, st, a);
+      hipLaunchKernelGGL(k, dim3(1), dim3(kPrefixNT), rq.lds, st, a);
       return hipGetLastError();
     }
     case LW_FINALIZE_MULTI: {
@@ -228,6 +238,13 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       } else {
         hipLaunchKernelGGL((pf_island_gather<D, MK, T, S>), dim3(rq.grid), dim3(256), 0, st, a);
       }
+      return hipGetLastError();
+    }
+    case LW_GLOBAL_SYS_DRAW: {
+      auto k = pf_global_sys_draw<D, MK, T, S, 256>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a, rq.tile_elems);
       return hipGetLastError();
     }
     case LW_GLOBAL_DRAW: {

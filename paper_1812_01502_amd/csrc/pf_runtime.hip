@@ -67,6 +67,8 @@ struct pf_handle {
   void* gcdf = nullptr;
   void* gcoarse = nullptr;
   void* gx = nullptr;
+  uint32_t* gfirst = nullptr;  // systematic global draw: first output per tile, then the work items
+  uint32_t* gwork = nullptr;
   double* gpre = nullptr;
   double* gscale = nullptr;
   uint32_t g_tile = 0, g_ntiles = 0, g_nt = 256, g_ppt = 1;
@@ -176,6 +178,8 @@ template <typename T, typename S> void fill_common(pf_handle* h, StepArgs<T, S>&
   a.gx = reinterpret_cast<S*>(h->gx);
   a.gpre = h->gpre;
   a.gscale = h->gscale;
+  a.gfirst = h->gfirst;
+  a.gwork = h->gwork;
 }
 
 template <typename T, typename S>
@@ -517,14 +521,21 @@ pf_status run_step(pf_handle* h, const double* y_host, const void* y_dev) {
     rq.lds = 0;
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global prefix launch");
-    rq.what = LW_GLOBAL_DRAW;
     rq.nt = 256;
-    rq.ppt = kDrawPPT;
-    const uint64_t pairs_per_block = 256ull * kDrawPPT;
-    rq.nchunks = (uint32_t)((h->N / 2 + pairs_per_block - 1) / pairs_per_block);
-    rq.grid = std::min<uint32_t>(rq.nchunks, kDrawBlocks);
-    rq.lds = h->g_ntiles <= 4096 ? (size_t)(h->g_ntiles + 1) * 8 : 16;
     rq.tile_elems = h->g_tile;
+    if (h->gwork != nullptr) {
+      // systematic: the merge over the items kernel 2 planned
+      rq.what = LW_GLOBAL_SYS_DRAW;
+      rq.grid = (uint32_t)std::min<uint64_t>(sys_max_items(h->N, h->g_ntiles), kDrawBlocks);
+      rq.lds = sys_draw_lds(h->D, h->tsz, h->ssz, h->g_tile);
+    } else {
+      rq.what = LW_GLOBAL_DRAW;
+      rq.ppt = kDrawPPT;
+      const uint64_t pairs_per_block = 256ull * kDrawPPT;
+      rq.nchunks = (uint32_t)((h->N / 2 + pairs_per_block - 1) / pairs_per_block);
+      rq.grid = std::min<uint32_t>(rq.nchunks, kDrawBlocks);
+      rq.lds = h->g_ntiles <= 4096 ? (size_t)(h->g_ntiles + 1) * 8 : 16;
+    }
     e = launch(h, rq, &a);
     if (e != hipSuccess) return hip_fail(h, e, "global draw launch");
     // the global path does not store log-weights: after it every one is 0
@@ -1004,14 +1015,22 @@ pf_status pf_create(const pf_model* model, const pf_config* cfg, void* hip_strea
   if (h->global) {
     // d = 1: the CDF in runs of 16 paired with the states (2 N values);
     // d > 1: the CDF (N) and the states particle-major (N D storage values)
-    if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz * (h->D == 1 ? 2 : 1))) != PF_OK) return bail(s);
-    if (h->D > 1 && (s = dalloc(h, &h->gx, (size_t)N * h->D * h->ssz)) != PF_OK) return bail(s);
+    // (systematic: the CDF alone; its draw reads the states where they are)
+    const bool sys = h->resampler == PF_RESAMPLE_SYSTEMATIC;
+    if ((s = dalloc(h, &h->gcdf, (size_t)N * h->tsz * (h->D == 1 && !sys ? 2 : 1))) != PF_OK) return bail(s);
+    if (h->D > 1 && !sys && (s = dalloc(h, &h->gx, (size_t)N * h->D * h->ssz)) != PF_OK) return bail(s);
     if ((s = dalloc(h, &h->gcoarse, (size_t)global_coarse_elems(N, h->g_ntiles) * h->tsz)) != PF_OK)
       return bail(s);
     if ((s = dalloc(h, &p, (size_t)(h->g_ntiles + 1) * 8)) != PF_OK) return bail(s);
     h->gpre = reinterpret_cast<double*>(p);
     if ((s = dalloc(h, &p, (size_t)h->g_ntiles * 8)) != PF_OK) return bail(s);
     h->gscale = reinterpret_cast<double*>(p);
+    if (h->resampler == PF_RESAMPLE_SYSTEMATIC) {
+      if ((s = dalloc(h, &p, (size_t)(h->g_ntiles + 1) * 4)) != PF_OK) return bail(s);
+      h->gfirst = reinterpret_cast<uint32_t*>(p);
+      if ((s = dalloc(h, &p, (size_t)(2 + 2 * sys_max_items(N, h->g_ntiles)) * 4)) != PF_OK) return bail(s);
+      h->gwork = reinterpret_cast<uint32_t*>(p);
+    }
   }
   s = do_init(h);
   if (s != PF_OK) return bail(s);

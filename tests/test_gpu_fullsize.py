@@ -78,6 +78,18 @@ def test_sv_n2p24_global_f32_and_bf16():
     _run("c3", 1 << 24, 1 << 24, steps=[1], dtype="bf16")
 
 
+def test_sv_n2p24_global_systematic():
+    """SV, N = 2^24, the global filter with systematic resampling: the merge
+    draw over the prefix kernel's items, at the benchmarked shape."""
+    _run("c3", 1 << 24, 1 << 24, steps=[0, 1], resampler="systematic")
+
+
+def test_lg8_n2p20_global_systematic():
+    """8-D LG, N = 2^20, the global filter with systematic resampling (the
+    states gathered from the particle-major copy)."""
+    _run("c2", 1 << 20, 1 << 20, steps=[1], resampler="systematic")
+
+
 def test_sv_n2p24_radix1024_bf16():
     """SV, N = 2^24, radix 1024 with BF16 states: the block path at stride
     1024."""

@@ -88,6 +88,14 @@ CASES = [
     ("ar1", 128, 2, "multinomial", "f32"),
     ("ar1", 128, 128, "multinomial", "f32"),
     ("lg8", 128, 64, "systematic", "f32"),
+    # the systematic global draw at every weight-tile size (d = 1: 4096,
+    # d = 4: 2048, d = 8: 1024; below 4096 particles: 128) and every dtype
+    ("sv", 65536, 65536, "systematic", "f32"),
+    ("sv", 16384, 16384, "systematic", "bf16"),
+    ("lg4dense", 8192, 8192, "systematic", "f32"),
+    ("lg8", 16384, 16384, "systematic", "f32"),
+    ("ar1", 1024, 1024, "systematic", "f64"),
+    ("ar1", 128, 128, "systematic", "f32"),
 ]
 
 
@@ -286,4 +294,37 @@ def test_full_cycle_step(model_name, N, radix, resampler, dtype):
             s = compare_full_cycle_step(flt, orc, st.x, st.logw, t, ys[t], st.log_norm, label)
             log(f"   ok sure={s['sure']:.4f} dw={s['max_dw']:.2e} dx={s['max_dx']:.2e}")
         st, _ = orc.step(st, ys[t], keep=False)
+    flt.close()
+
+
+@pytest.mark.parametrize("case", ["one_tile", "last_particle", "alternate_tiles"])
+def test_global_systematic_concentrated_weights(case):
+    """The systematic global draw when the weight sits on few particles: one
+    weight tile takes nearly every output (its outputs split into several
+    items), the last particle takes nearly all (targets near the total), or
+    every other tile has no weight (tiles without outputs). Start states
+    from the oracle, log-weights set on both sides, one step compared."""
+    model = MODELS["sv"]()
+    N = 1 << 16
+    orc = ButterflyOracle(model, N, N, "systematic", seed=31, stream_id=4)
+    flt = _filter(model, N, N, "systematic", "f32", seed=31, sid=4)
+    st = orc.init()
+    _, ys = W.simulate(model, 2, seed=8)
+    rng = np.random.Generator(np.random.PCG64(17))
+    logw = np.full(N, -40.0)
+    if case == "one_tile":
+        logw[3 * 4096:4 * 4096] = rng.normal(0.0, 1.0, 4096)
+    elif case == "last_particle":
+        logw[-1] = 0.0
+        logw[-5:-1] = -3.0
+    else:
+        tiles = np.arange(N) // 4096
+        # weights that underflow to zero against the others (FP64 too)
+        logw = np.where(tiles % 2 == 0, rng.normal(0.0, 0.5, N), -1e4)
+    label = f"sv N={N} global systematic {case}"
+    log(f"[case] {label}")
+    s = compare_one_step(flt, orc, st.x, logw, 0, ys[0], 0.0, label)
+    log(f"   ok flips={s['flips']} near={s['near']} dw={s['max_dw']:.2e}")
+    anc = flt.ancestors().astype(np.int64)
+    assert np.all(np.diff(anc) >= 0)  # systematic ancestors do not decrease
     flt.close()

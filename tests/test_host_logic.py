@@ -322,3 +322,141 @@ int main() {
         shutil.rmtree(d, ignore_errors=True)
     cases, bad = int(out[0]), int(out[1])
     assert cases == 2 * 5 * 2 * 40 * 64 * 4 and bad == 0, (cases, bad)
+
+
+def test_systematic_global_plan_and_offspring_ranges():
+    """The systematic global draw's plan and offspring ranges, built for the
+    host from the kernel header with AddressSanitizer: the first output of
+    every weight tile (sys_first_output, made non-decreasing), the items of
+    at most kSysItem outputs that the prefix kernel writes, and per item the
+    count of outputs below each CDF value (sys_outputs_below), whose
+    differences give each particle its outputs: every output is written
+    exactly once and gets exactly the ancestor of a plain search (the tile is
+    the number of tile prefixes <= the target, the position the number of the
+    tile's CDF entries <= the target's in-tile value, at most E - 1; a target
+    at the total takes the last particle). Tile sizes 128 .. 4096, zero-weight
+    tiles and particles, ties, weight concentrated on one tile (items split)
+    and on the last particle; no read or write leaves the arrays."""
+    import os
+    import re
+    import shutil
+    import subprocess
+    import tempfile
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ker = open(os.path.join(root, "paper_1812_01502_amd", "csrc", "pf_kernels.h")).read()
+    parts = [re.search(r"constexpr uint32_t kSysItem = .*?\n", ker).group(0),
+             re.search(r"__host__ __device__ constexpr uint64_t sys_max_items\(.*?\n}\n", ker, re.S).group(0),
+             re.search(r"__device__ __forceinline__ double sys_target\(.*?\n}\n", ker, re.S).group(0),
+             re.search(r"__device__ inline uint64_t sys_first_output\(.*?\n}\n", ker, re.S).group(0),
+             re.search(r"template <typename T>\n__device__ __forceinline__ T sys_value\(.*?\n}\n", ker, re.S).group(0),
+             re.search(r"template <typename T>\n__device__ inline uint32_t sys_outputs_below\(.*?\n}\n",
+                       ker, re.S).group(0)]
+    src = ("#define __device__\n#define __host__\n#define __forceinline__ inline\n"
+           "#include <cstdint>\n#include <cstddef>\n#include <cstdio>\n#include <random>\n#include <vector>\n"
+           "#include <cmath>\n#include <algorithm>\n" + "\n".join(parts) + r'''
+// mode 0: mixed weights; 1: one tile holds almost all; 2: the last particle holds almost all
+long check(uint32_t E, uint32_t nt, int mode, std::mt19937& g, long& cases) {
+  const uint64_t N = (uint64_t)E * nt;
+  std::vector<float> cdf(N);
+  std::vector<double> pre(nt + 1), rs(nt);
+  pre[0] = 0.0;
+  const uint32_t heavy = g() % nt;
+  for (uint32_t b = 0; b < nt; ++b) {
+    float acc = 0.f;
+    for (uint32_t q = 0; q < E; ++q) {
+      const uint32_t kind = g() % 8u;
+      float w = kind < 2 ? 0.f : (kind == 2 ? 1.f : (float)(g() % 1000u) * 1e-3f);
+      if (mode == 2) w = (b == nt - 1 && q == E - 1) ? 1.f : 1e-9f;
+      acc += w;
+      cdf[(uint64_t)b * E + q] = acc;
+    }
+    double ev = (g() % 6u == 0u) ? 0.0 : std::ldexp(1.0 + (double)(g() % 1000u) * 1e-3, -(int)(g() % 8u));
+    if (mode == 1) ev = b == heavy ? 1.0 : 1e-7;
+    if (mode == 2) ev = 1.0;
+    rs[b] = 1.0 / ev;
+    pre[b + 1] = pre[b] + ev * (double)acc;
+  }
+  const double total = pre[nt];
+  if (!(total > 0.0)) return 0;
+  const double scale = total / (double)N, inv_scale = (double)N / total;
+  long bad = 0;
+  for (int trial = 0; trial < 6; ++trial) {
+    const double u0 = (double)(g() >> 8) * 0x1p-24;
+    // plan: first output per tile, non-decreasing; then the items
+    std::vector<uint32_t> first(nt + 1);
+    uint32_t omax = 0;
+    for (uint32_t b = 0; b < nt; ++b) {
+      const uint32_t o = (uint32_t)sys_first_output(pre[b], u0, scale, N);
+      omax = std::max(omax, o);
+      first[b] = omax;
+    }
+    first[nt] = (uint32_t)N;
+    std::vector<uint32_t> items;
+    for (uint32_t b = 0; b < nt; ++b)
+      for (uint32_t o = first[b]; o < first[b + 1]; o += kSysItem) { items.push_back(b); items.push_back(o); }
+    if (items.size() / 2 > sys_max_items(N, nt)) ++bad;
+    std::vector<int64_t> anc(N, -1);
+    for (size_t w = 0; w < items.size() / 2; ++w) {
+      const uint32_t b = items[2 * w], start = items[2 * w + 1];
+      const uint32_t lim = first[b + 1];
+      const uint32_t end = lim - start > kSysItem ? start + kSysItem : lim;
+      const uint32_t n = end - start;
+      const float* t = cdf.data() + (uint64_t)b * E;
+      std::vector<uint16_t> sf(E);
+      std::vector<int> spos(n, -1);
+      for (uint32_t q = 0; q < E; ++q)
+        sf[q] = (uint16_t)sys_outputs_below<float>(t[q], n, start, u0, u0 + (double)start, scale, inv_scale,
+                                                   total, pre[b], rs[b], 1.0 / rs[b]);
+      for (uint32_t q = 0; q < E; ++q) {
+        const uint32_t lo = q == 0 ? 0u : sf[q - 1], hi = q == E - 1 ? n : sf[q];
+        for (uint32_t j = lo; j < hi; ++j) {
+          if (spos.at(j) != -1) ++bad;   // an output written twice
+          spos.at(j) = (int)q;
+        }
+      }
+      for (uint32_t j = 0; j < n; ++j) {
+        if (spos[j] < 0) { ++bad; continue; }   // an output never written
+        if (anc[start + j] != -1) ++bad;
+        anc[start + j] = (int64_t)b * E + spos[j];
+      }
+    }
+    // the plain search
+    for (uint64_t i = 0; i < N; ++i) {
+      ++cases;
+      const double tg = sys_target(i, u0, scale);
+      uint32_t b = 0;
+      for (uint32_t k = 1; k <= nt; ++k) if (pre[k] <= tg) b = k;
+      float lt;
+      if (b >= nt) { b = nt - 1; lt = INFINITY; } else { lt = (float)((tg - pre[b]) * rs[b]); }
+      uint32_t c = 0;
+      for (uint32_t q = 0; q < E; ++q) c += cdf[(uint64_t)b * E + q] <= lt ? 1u : 0u;
+      const int64_t want = (int64_t)b * E + std::min(c, E - 1u);
+      if (anc[i] != want) ++bad;
+    }
+  }
+  return bad;
+}
+int main() {
+  std::mt19937 g(5);
+  long cases = 0, bad = 0;
+  for (uint32_t E : {128u, 512u, 1024u, 2048u, 4096u})
+    for (uint32_t nt : {1u, 4u, 9u})
+      for (int mode : {0, 1, 2}) bad += check(E, nt, mode, g, cases);
+  bad += check(128u, 160u, 1, g, cases) + check(4096u, 5u, 1, g, cases);
+  printf("%ld %ld\n", cases, bad);
+  return 0;
+}
+''')
+    d = tempfile.mkdtemp()
+    try:
+        open(os.path.join(d, "s.cpp"), "w").write(src)
+        subprocess.run([cxx, "-O1", "-g", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        os.path.join(d, "s.cpp"), "-o", os.path.join(d, "s")], check=True)
+        out = subprocess.run([os.path.join(d, "s")], capture_output=True, text=True, check=True).stdout.split()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    cases, bad = int(out[0]), int(out[1])
+    assert cases > 1_000_000 and bad == 0, (cases, bad)
