@@ -64,6 +64,9 @@ constexpr int ppt_block(int D) { return D <= 2 ? 8 : (D <= 4 ? 4 : (D <= 8 ? 2 :
 // Pairs per thread of the global weight kernel (256 threads).
 constexpr int ppt_gweight(int D) { return D <= 2 ? 8 : (D == 4 ? 4 : (D == 8 ? 2 : 1)); }
 constexpr int kDrawPPT = 2;
+// Threads per block of the systematic global draw: 512 where the registers
+// allow two blocks per compute unit.
+constexpr int sys_draw_nt(int D) { return D <= 2 ? 512 : 256; }
 // Threads of the one-block global prefix kernel.
 constexpr int kPrefixNT = 1024;
 // LDS of the systematic global draw: d = 1, the tile's states; the output
@@ -241,10 +244,10 @@ static hipError_t launch_model(const LaunchReq& rq, const StepArgs<T, S>& a, hip
       return hipGetLastError();
     }
     case LW_GLOBAL_SYS_DRAW: {
-      auto k = pf_global_sys_draw<D, MK, T, S, 256>;
+      auto k = pf_global_sys_draw<D, MK, T, S, sys_draw_nt(D)>;
       hipError_t e = ensure_lds(k, rq.lds);
       if (e != hipSuccess) return e;
-      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a, rq.tile_elems);
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(sys_draw_nt(D)), rq.lds, st, a, rq.tile_elems);
       return hipGetLastError();
     }
     case LW_GLOBAL_DRAW: {
