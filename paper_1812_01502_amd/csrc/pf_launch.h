@@ -120,6 +120,13 @@ static hipError_t launch_step_tile(const LaunchReq& rq, const StepArgs<T, S>& a,
       hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
       return hipGetLastError();
     }
+    if (rq.nt == 256 && rq.ppt == 2) {
+      auto k = pf_step_tile<D, MK, T, S, 256, 2, true, FULL>;
+      hipError_t e = ensure_lds(k, rq.lds);
+      if (e != hipSuccess) return e;
+      hipLaunchKernelGGL(k, dim3(rq.grid), dim3(256), rq.lds, st, a);
+      return hipGetLastError();
+    }
   }
   if (rq.nt == 256 && rq.ppt == 1) {
     auto k = pf_step_tile<D, MK, T, S, 256, 1, true, FULL>;

@@ -702,7 +702,12 @@ pf_status plan_butterfly(uint64_t N, uint64_t radix, int D, int d, size_t tsz, b
       // 256-thread tiles of at least two groups; larger tiles give longer
       // contiguous rows at wide strides
       const uint32_t pb = (uint32_t)ppt_block(D);
-      if (D <= 2 && sp.r <= 256 && N >= 2048u) {
+      // d <= 2: tiles whose registers leave several blocks per compute unit
+      // (two pairs per thread: 74 VGPRs; four: 139; eight would hold 256)
+      if (D <= 2 && sp.r <= 256 && N >= 1024u) {
+        sp.nt = 256;
+        sp.ppt = 2;
+      } else if (D <= 2 && sp.r <= 1024 && N >= 2048u) {
         sp.nt = 256;
         sp.ppt = 4;
       } else if (512u * pb >= 2u * sp.r && 512u * pb <= N) {

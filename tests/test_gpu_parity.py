@@ -35,6 +35,7 @@ MODELS = {
     "lg4dense": lambda: W.dense_lg_model(4, 12),
     "lg8": lambda: W.lg8_model(seed=2),
     "lg3stable": lambda: W.random_stable_lg(3, 11),
+    "lg2stable": lambda: W.random_stable_lg(2, 13),
     "sv": lambda: W.sv_model(),
 }
 
@@ -96,6 +97,11 @@ CASES = [
     ("lg8", 16384, 16384, "systematic", "f32"),
     ("ar1", 1024, 1024, "systematic", "f64"),
     ("ar1", 128, 128, "systematic", "f32"),
+    # d = 2 (compiled dimension 2): the wave path and both block-path tiles
+    ("lg2stable", 8192, 64, "systematic", "f32"),
+    ("lg2stable", 16384, 256, "multinomial", "f32"),
+    ("lg2stable", 16384, 1024, "multinomial", "f32"),
+    ("lg2stable", 4096, 4096, "systematic", "f32"),
 ]
 
 
