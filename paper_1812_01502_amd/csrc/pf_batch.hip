@@ -51,8 +51,15 @@ struct ClassHost {
 
 }  // namespace
 
+// Streams besides the caller's over which the dimension classes of a step
+// are spread (the classes share no data, so their launches may overlap).
+constexpr int kAuxStreams = 3;
+
 struct pf_batch {
   hipStream_t stream = nullptr;
+  hipStream_t aux[kAuxStreams] = {};  // created with the batch when `stream` is not the null stream
+  hipEvent_t ev_fork = nullptr, ev_join[kAuxStreams] = {};
+  int naux = 0;
   uint32_t n = 0;
   uint32_t y_len = 0;
   std::vector<FilterHost> fh;
@@ -117,6 +124,35 @@ void bfree(pf_batch* b, void* p) {
 void brelease(pf_batch* b) {
   for (void* p : b->allocs) dev_free(b->dalloc_fn, p);
   b->allocs.clear();
+  for (int k = 0; k < b->naux; ++k) {
+    if (b->ev_join[k]) (void)hipEventDestroy(b->ev_join[k]);
+    if (b->aux[k]) (void)hipStreamDestroy(b->aux[k]);
+    b->ev_join[k] = nullptr;
+    b->aux[k] = nullptr;
+  }
+  if (b->ev_fork) (void)hipEventDestroy(b->ev_fork);
+  b->ev_fork = nullptr;
+  b->naux = 0;
+}
+
+// The streams the classes run on (default priority, not synchronising with
+// the null stream) and the events that fork them from and join them to the
+// caller's stream. Only with a caller's stream: work on the null stream is
+// not forked.
+pf_status create_aux_streams(pf_batch* b) {
+  if (!b->stream) return PF_OK;
+  hipError_t e = hipEventCreateWithFlags(&b->ev_fork, hipEventDisableTiming);
+  if (e != hipSuccess) return bhip(b, e, "event create");
+  for (int k = 0; k < kAuxStreams; ++k) {
+    e = hipStreamCreateWithFlags(&b->aux[k], hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&b->ev_join[k], hipEventDisableTiming);
+    if (e != hipSuccess) {
+      b->naux = k + 1;
+      return bhip(b, e, "class stream create");
+    }
+  }
+  b->naux = kAuxStreams;
+  return PF_OK;
 }
 
 // Stage tables of every filter for the current radices and class tiles;
@@ -247,30 +283,54 @@ pf_status init_all(pf_batch* b) {
   return PF_OK;
 }
 
-// One batched step: every class's step kernel, then every class's
-// reductions. No host data besides the two device pointers.
-pf_status batch_step(pf_batch* b, const float* y_dev, const uint8_t* active) {
+// Steps j = 0 .. n_steps - 1 (observations at y_dev + j y_stride): per
+// step, each class's step kernel, then its reductions. With `fork`, class i
+// runs on stream i mod (1 + naux) (0 = the caller's): the class streams wait
+// for the caller's stream first, and it waits for them at the end, so the
+// classes' launches may overlap (also inside a captured graph, as parallel
+// branches). No host data besides the device pointers.
+pf_status batch_steps(pf_batch* b, const float* y_dev, uint32_t n_steps, uint64_t y_stride,
+                      const uint8_t* active, bool fork) {
+  uint32_t nc = 0;
+  for (auto& c : b->classes) nc += c.filters.empty() ? 0u : 1u;
+  fork = fork && b->naux > 0 && nc > 1;
+  const int nstreams = fork ? std::min<int>(1 + b->naux, (int)nc) : 1;
+  hipError_t e;
+  if (fork) {
+    if ((e = hipEventRecord(b->ev_fork, b->stream)) != hipSuccess) return bhip(b, e, "fork event");
+    for (int k = 0; k + 1 < nstreams; ++k)
+      if ((e = hipStreamWaitEvent(b->aux[k], b->ev_fork, 0)) != hipSuccess) return bhip(b, e, "fork wait");
+  }
   BatchArgs a{};
   a.filt = b->d_filt;
   a.stages = b->d_stages;
   a.active = active;
-  a.y = y_dev;
   a.tcur = b->d_tcur;
-  for (auto& c : b->classes) {
-    if (c.filters.empty()) continue;
-    a.block_filter = c.d_block_filter;
-    BatchReq rq{0, c.D, c.mk, c.ppt, c.full, c.nblocks, c.lds};
-    hipError_t e = launch_batch(rq, a, b->stream);
-    if (e != hipSuccess) return bhip(b, e, "batched step launch");
+  for (uint32_t j = 0; j < n_steps; ++j) {
+    a.y = y_dev + (size_t)j * y_stride;
+    uint32_t ci = 0;
+    for (auto& c : b->classes) {
+      if (c.filters.empty()) continue;
+      const int k = (int)(ci++ % (uint32_t)nstreams);
+      hipStream_t st = k == 0 ? b->stream : b->aux[k - 1];
+      a.block_filter = c.d_block_filter;
+      BatchReq rq{0, c.D, c.mk, c.ppt, c.full, c.nblocks, c.lds};
+      if ((e = launch_batch(rq, a, st)) != hipSuccess) return bhip(b, e, "batched step launch");
+      a.class_filters = c.d_class_filters;
+      BatchReq rf{1, c.D, c.mk, c.ppt, c.full, (uint32_t)c.filters.size(), 0};
+      if ((e = launch_batch(rf, a, st)) != hipSuccess) return bhip(b, e, "batched finalize launch");
+    }
   }
-  for (auto& c : b->classes) {
-    if (c.filters.empty()) continue;
-    a.class_filters = c.d_class_filters;
-    BatchReq rq{1, c.D, c.mk, c.ppt, c.full, (uint32_t)c.filters.size(), 0};
-    hipError_t e = launch_batch(rq, a, b->stream);
-    if (e != hipSuccess) return bhip(b, e, "batched finalize launch");
+  if (fork) {
+    for (int k = 0; k + 1 < nstreams; ++k) {
+      if ((e = hipEventRecord(b->ev_join[k], b->aux[k])) != hipSuccess) return bhip(b, e, "join event");
+      if ((e = hipStreamWaitEvent(b->stream, b->ev_join[k], 0)) != hipSuccess) return bhip(b, e, "join wait");
+    }
   }
   return PF_OK;
+}
+pf_status batch_step(pf_batch* b, const float* y_dev, const uint8_t* active) {
+  return batch_steps(b, y_dev, 1, 0, active, false);
 }
 
 // Time `steps` batched steps (after `warm`) on the current plan, in ms.
@@ -587,6 +647,7 @@ pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_
     if ((s = upload_tables(b)) != PF_OK) return bail(s);
     if ((s = init_all(b)) != PF_OK) return bail(s);
   }
+  if ((s = create_aux_streams(b)) != PF_OK) return bail(s);
   if ((s = bsync(b)) != PF_OK) return bail(s);
   *out = b;
   return PF_OK;
@@ -604,7 +665,7 @@ pf_status pf_batch_step(pf_batch* b, const float* y_dev, const uint8_t* active_d
   if (!b) return PF_E_INVALID;
   if (bpoisoned(b)) return PF_E_STATE;
   if (!y_dev) return bfail(b, PF_E_INVALID, "y_dev is NULL");
-  return batch_step(b, y_dev, active_dev);
+  return batch_steps(b, y_dev, 1, 0, active_dev, true);
 }
 
 pf_status pf_batch_run(pf_batch* b, const float* y_dev, uint32_t n_steps, uint64_t y_stride,
@@ -619,8 +680,7 @@ pf_status pf_batch_run(pf_batch* b, const float* y_dev, uint32_t n_steps, uint64
     hipError_t e = hipStreamBeginCapture(b->stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return bhip(b, e, "hipStreamBeginCapture");
   }
-  pf_status st = PF_OK;
-  for (uint32_t j = 0; j < n_steps && st == PF_OK; ++j) st = batch_step(b, y_dev + (size_t)j * y_stride, active_dev);
+  pf_status st = batch_steps(b, y_dev, n_steps, y_stride, active_dev, true);
   if (use_graph) {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
