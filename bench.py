@@ -115,6 +115,51 @@ def cpu_baseline(model, N, radix, ys, budget_s=12.0):
                        f"(stage cycle {orc.plan}), FP64 NumPy, 1 thread, {el:.1f} s")
 
 
+def bf16_error(N: int = 1 << 16, radix: int = 64, T: int = 64, every: int = 8):
+    """Error that state storage adds to each result of one step, FP32 and BF16
+    against the FP64 instantiation of the same kernels (SV, N particles): at
+    every `every`-th step of an FP64 trajectory, the FP64 cloud is rounded to
+    the storage type, loaded into a filter of that type and stepped once;
+    the FP64 filter takes the same step from the exact cloud. Largest error
+    over the checkpoints: |d mean| / sd, |d var| / var, |d ESS| / ESS and
+    |d log-normaliser increment|, with the Monte Carlo sd of the mean / sd
+    (1 / sqrt(N ESS)) for scale."""
+    import numpy as np
+    import paper_1812_01502_amd as P
+    import workloads as W
+    model = W.sv_model()
+    _, ys = W.simulate(model, T, seed=3)
+    ref = P.Filter(model, N, radix, dtype="f64", seed=303)
+    low = {dt: P.Filter(model, N, radix, dtype=dt, seed=303) for dt in ("f32", "bf16")}
+    worst = {dt: dict(mean=0.0, var=0.0, ess=0.0, log_norm=0.0) for dt in low}
+    mc = 0.0
+    for t in range(T):
+        if t % every == every - 1:
+            x, w, tt, ln = ref.get_state()
+            for dt, f in low.items():
+                x32 = x.astype(np.float32)
+                f.set_state(P.f32_to_bf16(x32) if dt == "bf16" else x32, w.astype(np.float32), t=tt, log_norm=0.0)
+                f.step(ys[t])
+        ref.step(ys[t])
+        if t % every == every - 1:
+            e0 = ref.estimate()
+            sd = float(np.sqrt(e0["var"][0]))
+            mc = max(mc, 1.0 / np.sqrt(N * e0["ess"]))
+            dlam0 = e0["log_norm"] - ln
+            for dt, f in low.items():
+                e = f.estimate()
+                wd = worst[dt]
+                wd["mean"] = max(wd["mean"], abs(e["mean"][0] - e0["mean"][0]) / sd)
+                wd["var"] = max(wd["var"], abs(e["var"][0] - e0["var"][0]) / e0["var"][0])
+                wd["ess"] = max(wd["ess"], abs(e["ess"] - e0["ess"]) / e0["ess"])
+                wd["log_norm"] = max(wd["log_norm"], abs(e["log_norm"] - dlam0))
+    for f in [ref, *low.values()]:
+        f.close()
+    return {"workload": f"SV, N = {N}, radix {radix}, one step from the FP64 cloud at {T // every} steps "
+                        f"of a {T}-step trajectory; reference: the FP64 kernels",
+            "f32": worst["f32"], "bf16": worst["bf16"], "mc_sd_of_mean_over_sd": mc}
+
+
 def batched_bench(steps: int, warmup: int):
     """The batched workload: 4096 independent LG filters, N_f = 2^u with u
     uniform in 10..16, d_f uniform over {1, 4, 16}, seeded stable A, radix and
@@ -513,6 +558,7 @@ def main():
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"],
                           "mean": float(est["mean"][0])},
     }
+    out["bf16_error"] = safe(bf16_error)
     if not args.no_batch:
         out["batched"] = safe(batched_bench, 200, 5)
     if not args.no_serve:
