@@ -526,6 +526,7 @@ def main():
     achieved = launch_bytes / avg_launch_s / 1e9
     traffic = load_traffic(PROFILE_SUMMARY.get(("sv", args.radix, "f32")))
     gf = sv["global_bpf"].get("f32", {})
+    gs = sv.get("systematic", {}).get("global f32", {})
 
     out = {
         "metric": "particle-steps/s + %HBM roofline, butterfly vs global BPF; p99 step latency",
@@ -553,6 +554,9 @@ def main():
         "latency_us": {"p50": p50, "p99": p99, "mean": mean_us},
         "speedup_butterfly_over_global": (head["particle_steps_per_s"] / gf["particle_steps_per_s"]
                                           if "particle_steps_per_s" in gf else None),
+        # against the faster global filter: systematic resampling by offspring ranges
+        "speedup_butterfly_over_global_systematic": (
+            head["particle_steps_per_s"] / gs["particle_steps_per_s"] if "particle_steps_per_s" in gs else None),
         "sv": sv,
         "lg8": lg8,
         "last_estimate": {"t": est["t"], "ess": est["ess"], "log_norm": est["log_norm"],
