@@ -1506,11 +1506,12 @@ __device__ __forceinline__ double sys_target(uint32_t i, double u0, double scale
   return ((double)i + u0) * scale;
 }
 // Smallest i in [0, N] whose target reaches p (N when none below N does):
-// a guess from the inverse of the target, checked, then halving.
-__device__ inline uint64_t sys_first_output(double p, double u0, double scale, uint64_t N) {
+// a guess from the inverse of the target (inv_scale = 1 / scale), checked,
+// then halving.
+__device__ inline uint64_t sys_first_output(double p, double u0, double scale, double inv_scale, uint64_t N) {
   auto reaches = [&](uint64_t i) { return i >= N || sys_target((uint32_t)i, u0, scale) >= p; };
   uint64_t lo = 0, hi = N;  // the answer lies in [lo, hi]
-  const double x = scale > 0.0 ? p / scale - u0 : 0.0;
+  const double x = scale > 0.0 ? p * inv_scale - u0 : 0.0;
   if (x > 2.0 && x < (double)N - 3.0) {  // false for a NaN
     const uint64_t g = (uint64_t)x;
     if (!reaches(g - 2u)) lo = g - 1u;
@@ -1711,15 +1712,48 @@ __global__ void __launch_bounds__(NT) pf_global_weight(StepArgs<T, S> a) {
   if (tid == 0) prt[1] = tot;  // the tile's weight sum is the CDF total (same rounding as the CDF)
 }
 
+// Block-wide exclusive scan of NT threads under `op` (identity `ident`): a
+// wave pass by shuffles, then one exchange of the wave totals through LDS
+// (sw: NT / 64 entries, free again on return). `total` gets the block's.
+template <int NT, typename V, typename Op>
+__device__ __forceinline__ V block_excl_scan(V v, Op op, V ident, V* sw, V& total) {
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  V x = v;
+#pragma unroll
+  for (int s = 1; s < 64; s <<= 1) {
+    const V o = __shfl_up(x, (unsigned)s, 64);
+    if (lane >= s) x = op(x, o);
+  }
+  if (lane == 63) sw[wv] = x;
+  V ex = __shfl_up(x, 1u, 64);
+  if (lane == 0) ex = ident;
+  __syncthreads();
+  V before = ident, tot = ident;
+#pragma unroll
+  for (int w = 0; w < NT / 64; ++w) {
+    if (w < wv) before = op(before, sw[w]);
+    tot = op(tot, sw[w]);
+  }
+  __syncthreads();
+  total = tot;
+  return op(before, ex);
+}
+
 // Global path, kernel 2 (one block): tile prefix in FP64; every new
 // log-weight is equal, so the next offset is 0. Each thread owns a
-// contiguous run of tiles and issues the loads of up to 16 of them before it
-// uses any.
+// contiguous run of tiles and issues the loads of a chunk of them before it
+// uses any; the block's reductions and scans run by wave shuffles.
 template <int D, typename T, typename S, int NT>
 __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
-  __shared__ double sd[NT];
+  __shared__ double swd[NT / 64];
+  __shared__ uint32_t swu[NT / 64];
+  __shared__ uint32_t sfirst[NT + 1];
   constexpr int PS = partial_stride(D);
   constexpr uint32_t CH = NT >= 1024 ? 4 : 16;
+  auto dmax = [](double x, double y) { return fmax(x, y); };
+  auto dadd = [](double x, double y) { return x + y; };
+  auto umax = [](uint32_t x, uint32_t y) { return x > y ? x : y; };
+  auto uadd = [](uint32_t x, uint32_t y) { return x + y; };
   const T* part = a.part_out;
   const uint32_t nt = a.ntiles;
   const int tid = threadIdx.x;
@@ -1733,14 +1767,8 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
 #pragma unroll
     for (uint32_t k = 0; k < CH; ++k) m = fmax(m, (double)mv[k]);
   }
-  sd[tid] = m;
-  __syncthreads();
-  for (int s = NT / 2; s > 0; s >>= 1) {
-    if (tid < s) sd[tid] = fmax(sd[tid], sd[tid + s]);
-    __syncthreads();
-  }
-  const double M = sd[0];
-  __syncthreads();
+  double M;
+  (void)block_excl_scan<NT>(m, dmax, (double)-INFINITY, swd, M);
   // exclusive prefix of T_b = S_b e^{m_b - M}: contiguous runs per thread
   double loc = 0.0;
   for (uint32_t c = b0; c < b1; c += CH) {
@@ -1760,19 +1788,12 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
       }
     }
   }
-  sd[tid] = loc;
-  __syncthreads();
-  for (int s = 1; s < NT; s <<= 1) {
-    const double o = tid >= s ? sd[tid - s] : 0.0;
-    __syncthreads();
-    sd[tid] += o;
-    __syncthreads();
-  }
-  double run = sd[tid] - loc;
+  double total;
+  double run = block_excl_scan<NT>(loc, dadd, 0.0, swd, total);
   // systematic: the first output of each tile, from its prefix
   const bool plan = a.systematic && a.gwork != nullptr;
   const uint64_t N = a.N;
-  const double scale = sd[NT - 1] / (double)N;
+  const double scale = total / (double)N, inv_scale = (double)N / total;
   const double u0 = plan ? word_uniform<double>(philox(0u, a.t + 1u, 0u, a.sid, a.k0, a.k1).w0) : 0.0;
   uint32_t ofirst = 0, omax = 0, cnt = 0;
   for (uint32_t c = b0; c < b1; c += CH) {
@@ -1790,7 +1811,7 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
         a.gpre[c + k] = run;
         if (plan) {
           // non-decreasing within the thread; the items of the tile before
-          const uint32_t o = (uint32_t)sys_first_output(run, u0, scale, N);
+          const uint32_t o = (uint32_t)sys_first_output(run, u0, scale, inv_scale, N);
           const uint32_t om = o > omax ? o : omax;
           if (c + k == b0) {
             ofirst = om;
@@ -1807,27 +1828,18 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
       }
     }
   }
-  if (tid == NT - 1) a.gpre[nt] = sd[NT - 1];
+  if (tid == NT - 1) a.gpre[nt] = total;
   if (plan) {
     // the tiles' ranges split [0, N) exactly: the first outputs are made
     // non-decreasing over the block (the last tile also takes any target at
     // the total); then each tile's items of at most kSysItem outputs
-    __shared__ uint32_t su[NT];
-    __shared__ uint32_t sfirst[NT + 1];
     const bool has = b0 < b1;
-    su[tid] = omax;
-    __syncthreads();
-    for (int s = 1; s < NT; s <<= 1) {
-      const uint32_t o = tid >= s ? su[tid - s] : 0u;
-      __syncthreads();
-      su[tid] = o > su[tid] ? o : su[tid];
-      __syncthreads();
-    }
-    const uint32_t before = tid > 0 ? su[tid - 1] : 0u;
+    uint32_t omax_all;
+    const uint32_t before = block_excl_scan<NT>(omax, umax, 0u, swu, omax_all);
     sfirst[tid] = has ? (ofirst > before ? ofirst : before) : (uint32_t)N;
     if (tid == 0) sfirst[NT] = (uint32_t)N;
     if (tid == 0) a.gfirst[nt] = (uint32_t)N;
-    __syncthreads();
+    __syncthreads();  // sfirst, and every entry of gfirst (this block's global writes)
     const uint32_t next = sfirst[tid + 1];
     if (has) {
       if (ofirst < before) {
@@ -1845,16 +1857,8 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
       const uint32_t last = omax > before ? omax : before;
       cnt += (next - last + kSysItem - 1u) / kSysItem;
     }
-    __syncthreads();
-    su[tid] = cnt;
-    __syncthreads();
-    for (int s = 1; s < NT; s <<= 1) {
-      const uint32_t o = tid >= s ? su[tid - s] : 0u;
-      __syncthreads();
-      su[tid] += o;
-      __syncthreads();
-    }
-    uint32_t wi = su[tid] - cnt;
+    uint32_t nwork;
+    uint32_t wi = block_excl_scan<NT>(cnt, uadd, 0u, swu, nwork);
     for (uint32_t c = b0; c < b1; c += CH) {
       uint32_t of[CH + 1];
 #pragma unroll
@@ -1872,7 +1876,7 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
         }
       }
     }
-    if (tid == NT - 1) a.gwork[0] = su[NT - 1];
+    if (tid == 0) a.gwork[0] = nwork;
   }
   if (tid == 0) *off_slot(a.ctl, a.u + 1, 0) = ord_encode(0.0);
   step_bookkeeping(a);

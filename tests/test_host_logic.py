@@ -389,7 +389,7 @@ long check(uint32_t E, uint32_t nt, int mode, std::mt19937& g, long& cases) {
     std::vector<uint32_t> first(nt + 1);
     uint32_t omax = 0;
     for (uint32_t b = 0; b < nt; ++b) {
-      const uint32_t o = (uint32_t)sys_first_output(pre[b], u0, scale, N);
+      const uint32_t o = (uint32_t)sys_first_output(pre[b], u0, scale, inv_scale, N);
       omax = std::max(omax, o);
       first[b] = omax;
     }
