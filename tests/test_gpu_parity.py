@@ -36,6 +36,7 @@ MODELS = {
     "lg8": lambda: W.lg8_model(seed=2),
     "lg3stable": lambda: W.random_stable_lg(3, 11),
     "lg2stable": lambda: W.random_stable_lg(2, 13),
+    "lg16stable": lambda: W.random_stable_lg(16, 17),
     "sv": lambda: W.sv_model(),
 }
 
@@ -102,6 +103,12 @@ CASES = [
     ("lg2stable", 16384, 256, "multinomial", "f32"),
     ("lg2stable", 16384, 1024, "multinomial", "f32"),
     ("lg2stable", 4096, 4096, "systematic", "f32"),
+    # d = 16 (the largest compiled dimension): wave path, block path, both
+    # global draws
+    ("lg16stable", 8192, 64, "multinomial", "f32"),
+    ("lg16stable", 8192, 256, "systematic", "f32"),
+    ("lg16stable", 4096, 4096, "multinomial", "f32"),
+    ("lg16stable", 4096, 4096, "systematic", "f32"),
 ]
 
 
