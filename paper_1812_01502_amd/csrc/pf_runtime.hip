@@ -703,8 +703,9 @@ pf_status plan_butterfly(uint64_t N, uint64_t radix, int D, int d, size_t tsz, b
       // contiguous rows at wide strides
       const uint32_t pb = (uint32_t)ppt_block(D);
       // d <= 2: tiles whose registers leave several blocks per compute unit
-      // (two pairs per thread: 74 VGPRs; four: 139; eight would hold 256)
-      if (D <= 2 && sp.r <= 256 && N >= 1024u) {
+      // (two pairs per thread: 74 VGPRs; four: 139; eight would hold 256); a
+      // stride-1 stage may hold a single group per tile
+      if (D <= 2 && ((sp.r <= 256 && N >= 1024u) || (sp.r <= 1024 && sp.log2R == 0 && N >= 1024u))) {
         sp.nt = 256;
         sp.ppt = 2;
       } else if (D <= 2 && sp.r <= 1024 && N >= 2048u) {
