@@ -290,7 +290,13 @@ typedef struct {
  * tile size, the largest radix within 10 % of the fastest time (see
  * pf_batch_tuning). cfgs[i].history and the dtype other than F32 are not
  * supported (history is 1). Errors as pf_create; the message of a failed
- * create is pf_batch_last_error(NULL). */
+ * create is pf_batch_last_error(NULL).
+ * hip_stream: the stream every call enqueues on (NULL: the null stream).
+ * With a non-null stream the batch also creates three streams of its own
+ * (default priority, released by pf_batch_destroy): pf_batch_step and
+ * pf_batch_run spread the classes of filters over them, forked from and
+ * joined back to hip_stream by events within the call, so work enqueued on
+ * hip_stream after a call sees all of it (also inside a captured graph). */
 pf_status pf_batch_create(const pf_model* models, const pf_config* cfgs, uint32_t n,
                           void* hip_stream, pf_batch** out);
 
