@@ -694,8 +694,11 @@ __device__ __forceinline__ void pair_coords(const TileGeo& g, uint32_t f, uint32
 // round-robin to the 8 XCDs; each XCD gets a contiguous range of tiles, so
 // neighbouring column chunks share the XCD's L2.
 __device__ __forceinline__ uint32_t xcd_tile(uint32_t b, uint32_t ntiles) {
-  if ((ntiles & 7u) != 0u) return b;
-  return (b & 7u) * (ntiles >> 3) + (b >> 3);
+  // the first 8 floor(ntiles / 8) blocks are remapped; a tail of fewer than
+  // 8 keeps its order
+  const uint32_t q = ntiles >> 3;
+  if (b >= 8u * q) return b;
+  return (b & 7u) * q + (b >> 3);
 }
 
 // Bump allocator over the dynamic LDS block: offsets are plain integers so
@@ -1397,7 +1400,10 @@ struct BatchArgs {
 template <int D, int MK, int NT, int PPT, bool FULL>
 __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   extern __shared__ __align__(16) unsigned char smem[];
-  const uint32_t f = ba.block_filter[blockIdx.x];
+  // the class's blocks in XCD order: neighbouring tiles of a filter, which
+  // share the L2 lines of their rows, run on one XCD
+  const uint32_t bi = xcd_tile(blockIdx.x, gridDim.x);
+  const uint32_t f = ba.block_filter[bi];
   if (ba.active && !ba.active[f]) return;
   const BatchFilter& F = ba.filt[f];
   const uint32_t t = ba.tcur[f];
@@ -1434,7 +1440,7 @@ __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   a.k1 = F.k1;
   a.systematic = F.systematic;
   a.lnr = sg.lnr;
-  step_tile_body<D, MK, float, float, NT, PPT, false, FULL>(a, blockIdx.x - F.first_block, smem);
+  step_tile_body<D, MK, float, float, NT, PPT, false, FULL>(a, bi - F.first_block, smem);
 }
 
 // Reduction of one filter's tile partials per block (after the class's

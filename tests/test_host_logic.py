@@ -460,3 +460,49 @@ int main() {
         shutil.rmtree(d, ignore_errors=True)
     cases, bad = int(out[0]), int(out[1])
     assert cases > 1_000_000 and bad == 0, (cases, bad)
+
+
+def test_xcd_tile_order_is_a_permutation():
+    """The XCD-aware block order (xcd_tile), built for the host from the
+    kernel header: for every grid size up to 4100 it is a permutation of the
+    blocks, and when the size is a multiple of 8 each XCD (block b on XCD
+    b mod 8) gets one contiguous range of tiles."""
+    import os
+    import re
+    import shutil
+    import subprocess
+    import tempfile
+    cxx = shutil.which("g++")
+    if cxx is None:
+        pytest.skip("no C++ compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    ker = open(os.path.join(root, "paper_1812_01502_amd", "csrc", "pf_kernels.h")).read()
+    fn = re.search(r"__device__ __forceinline__ uint32_t xcd_tile\(.*?\n}\n", ker, re.S).group(0)
+    src = ("#define __device__\n#define __forceinline__ inline\n#include <cstdint>\n#include <cstdio>\n"
+           "#include <vector>\n" + fn + r'''
+int main() {
+  long bad = 0;
+  for (uint32_t n = 1; n <= 4100; ++n) {
+    std::vector<int> seen(n, 0);
+    for (uint32_t b = 0; b < n; ++b) {
+      const uint32_t t = xcd_tile(b, n);
+      if (t >= n || seen[t]++) ++bad;
+    }
+    if (n % 8 == 0)
+      for (uint32_t x = 0; x < 8; ++x)
+        for (uint32_t j = 1; j < n / 8; ++j)
+          if (xcd_tile(x + 8 * j, n) != xcd_tile(x + 8 * (j - 1), n) + 1) ++bad;
+  }
+  printf("%ld\n", bad);
+  return 0;
+}
+''')
+    d = tempfile.mkdtemp()
+    try:
+        open(os.path.join(d, "s.cpp"), "w").write(src)
+        subprocess.run([cxx, "-O1", "-std=c++17", "-fsanitize=address,undefined", "-fno-sanitize-recover=all",
+                        os.path.join(d, "s.cpp"), "-o", os.path.join(d, "s")], check=True)
+        out = subprocess.run([os.path.join(d, "s")], capture_output=True, text=True, check=True).stdout.split()
+    finally:
+        shutil.rmtree(d, ignore_errors=True)
+    assert int(out[0]) == 0
