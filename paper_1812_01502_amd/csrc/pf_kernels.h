@@ -1400,9 +1400,11 @@ struct BatchArgs {
 template <int D, int MK, int NT, int PPT, bool FULL>
 __global__ void __launch_bounds__(NT) pf_batch_tile(BatchArgs ba) {
   extern __shared__ __align__(16) unsigned char smem[];
-  // the class's blocks in XCD order: neighbouring tiles of a filter, which
-  // share the L2 lines of their rows, run on one XCD
-  const uint32_t bi = xcd_tile(blockIdx.x, gridDim.x);
+  // without an active mask the class's blocks run in XCD order, so that
+  // neighbouring tiles of a filter, which share the L2 lines of their rows,
+  // run on one XCD; with a mask (some filters idle) launch order spreads the
+  // active filters' blocks evenly over the XCDs, which matters more
+  const uint32_t bi = ba.active ? blockIdx.x : xcd_tile(blockIdx.x, gridDim.x);
   const uint32_t f = ba.block_filter[bi];
   if (ba.active && !ba.active[f]) return;
   const BatchFilter& F = ba.filt[f];
