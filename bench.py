@@ -22,6 +22,7 @@ Usage: python bench.py [--steps K] [--warmup W] [--gpus 1]
        python bench.py --mode profile [--workload sv|lg8] [--radix R] [--dtype f32|bf16]
                        [--profile-island | --profile-adaptive | --profile-global]
                        (one filter's steps only, for rocprofv3)
+       python bench.py --mode copybw   (device copy rate at 64 MiB to 4 GiB)
 """
 from __future__ import annotations
 
@@ -399,6 +400,31 @@ def variants(L: Legs, radix: int, island_M: int):
     return out
 
 
+def copy_bandwidth(sizes_mib=(64, 128, 256, 512, 1024, 4096), reps=20):
+    """Device-to-device copy rate (bytes read + bytes written per second) of
+    torch's copy at several sizes, with HIP events around ``reps`` copies
+    after two untimed ones. Sizes above the 256 MB Infinity Cache give the
+    practical HBM ceiling that the step kernels are compared with."""
+    import torch
+    out = []
+    for mib in sizes_mib:
+        n = mib << 18   # float32 elements
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(2):
+            dst.copy_(src)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            dst.copy_(src)
+        e1.record()
+        torch.cuda.synchronize()
+        us = e0.elapsed_time(e1) * 1e3 / reps
+        out.append({"mib": mib, "us_per_copy": us, "gb_per_s": 2 * n * 4 / us / 1e3})
+        del src, dst
+    return out
+
+
 def profile_mode(args, L: Legs):
     """One filter's warm-up and timed steps (for rocprofv3), then a plain copy
     of known size (counter calibration)."""
@@ -434,7 +460,8 @@ def main():
     ap.add_argument("--dtype", choices=["f32", "bf16"], default="f32", help="--mode profile: state storage")
     ap.add_argument("--resampler", choices=["multinomial", "systematic"], default="multinomial",
                     help="--mode profile: resampler")
-    ap.add_argument("--mode", choices=["bench", "profile"], default="bench")
+    ap.add_argument("--mode", choices=["bench", "profile", "copybw"], default="bench",
+                    help="copybw: the device-to-device copy rate at several sizes (the practical HBM ceiling)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--workload", choices=["sv", "lg8"], default="sv",
                     help="--mode profile: sv (stochastic volatility, N = 2^24) or lg8 (8-D LG, N = 2^20)")
@@ -464,6 +491,9 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     P.load_library()
+    if args.mode == "copybw":
+        print(json.dumps({"copy_bandwidth": copy_bandwidth()}), flush=True)
+        return
     if args.batch_only:
         print(json.dumps({"batched": batched_bench(200, 5)}), flush=True)
         return
