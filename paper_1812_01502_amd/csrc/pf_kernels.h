@@ -1767,13 +1767,27 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   const int tid = threadIdx.x;
   const uint32_t per = (nt + NT - 1) / NT;
   const uint32_t b0 = tid * per, b1 = min(nt, b0 + per);
+  // When one chunk covers the thread's tiles (per <= CH, every tile count
+  // up to CH NT), their (m, S) and scales stay in registers from the first
+  // read on; otherwise each pass reads them again. The records are a
+  // stride apart, so every read is a separate line request, and the single
+  // block's request rate is what this kernel's time is made of.
+  const bool one = per <= CH;
+  T mk[CH], sk[CH];
+  double ek[CH];
+#pragma unroll
+  for (uint32_t k = 0; k < CH; ++k) mk[k] = sk[k] = (T)0, ek[k] = 0.0;
   double m = -INFINITY;
   for (uint32_t c = b0; c < b1; c += CH) {
-    T mv[CH];
 #pragma unroll
-    for (uint32_t k = 0; k < CH; ++k) mv[k] = c + k < b1 ? part[(size_t)(c + k) * PS] : (T)-INFINITY;
+    for (uint32_t k = 0; k < CH; ++k) {
+      const size_t b = (size_t)(c + k < b1 ? c + k : b0) * PS;
+      mk[k] = part[b];
+      sk[k] = part[b + 1];
+    }
 #pragma unroll
-    for (uint32_t k = 0; k < CH; ++k) m = fmax(m, (double)mv[k]);
+    for (uint32_t k = 0; k < CH; ++k)
+      if (c + k < b1) m = fmax(m, (double)mk[k]);
   }
   double M;
   (void)block_excl_scan<NT>(m, dmax, (double)-INFINITY, swd, M);
@@ -1784,14 +1798,15 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
 #pragma unroll
     for (uint32_t k = 0; k < CH; ++k) {
       const size_t b = (size_t)(c + k < b1 ? c + k : b0) * PS;
-      mv[k] = part[b];
-      sv[k] = part[b + 1];
+      mv[k] = one ? mk[k] : part[b];
+      sv[k] = one ? sk[k] : part[b + 1];
     }
 #pragma unroll
     for (uint32_t k = 0; k < CH; ++k) {
       if (c + k < b1) {
         const double e = exp((double)mv[k] - M);
-        a.gscale[c + k] = e;
+        ek[k] = e;
+        if (!one) a.gscale[c + k] = e;
         loc += e * (double)sv[k];
       }
     }
@@ -1804,14 +1819,17 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
   const double scale = total / (double)N, inv_scale = (double)N / total;
   const double u0 = plan ? word_uniform<double>(philox(0u, a.t + 1u, 0u, a.sid, a.k0, a.k1).w0) : 0.0;
   uint32_t ofirst = 0, omax = 0, cnt = 0;
+  uint32_t fk[CH];  // the tiles' first outputs (registers when one chunk)
+#pragma unroll
+  for (uint32_t k = 0; k < CH; ++k) fk[k] = 0;
   for (uint32_t c = b0; c < b1; c += CH) {
     T sv[CH];
     double ev[CH];
 #pragma unroll
     for (uint32_t k = 0; k < CH; ++k) {
       const uint32_t b = c + k < b1 ? c + k : b0;
-      sv[k] = part[(size_t)b * PS + 1];
-      ev[k] = a.gscale[b];
+      sv[k] = one ? sk[k] : part[(size_t)b * PS + 1];
+      ev[k] = one ? ek[k] : a.gscale[b];
     }
 #pragma unroll
     for (uint32_t k = 0; k < CH; ++k) {
@@ -1827,6 +1845,7 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
             cnt += (om - omax + kSysItem - 1u) / kSysItem;
           }
           omax = om;
+          fk[k] = om;
           a.gfirst[c + k] = om;
         }
         run += ev[k] * (double)sv[k];
@@ -1855,11 +1874,24 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
         // raise the thread's leading entries and count again
         cnt = 0;
         uint32_t prev = 0;
-        for (uint32_t b = b0; b < b1; ++b) {
-          const uint32_t o = a.gfirst[b] > before ? a.gfirst[b] : before;
-          a.gfirst[b] = o;
-          if (b > b0) cnt += (o - prev + kSysItem - 1u) / kSysItem;
-          prev = o;
+        if (one) {
+#pragma unroll
+          for (uint32_t k = 0; k < CH; ++k) {
+            if (b0 + k < b1) {
+              const uint32_t o = fk[k] > before ? fk[k] : before;
+              fk[k] = o;
+              a.gfirst[b0 + k] = o;
+              if (k > 0) cnt += (o - prev + kSysItem - 1u) / kSysItem;
+              prev = o;
+            }
+          }
+        } else {
+          for (uint32_t b = b0; b < b1; ++b) {
+            const uint32_t o = a.gfirst[b] > before ? a.gfirst[b] : before;
+            a.gfirst[b] = o;
+            if (b > b0) cnt += (o - prev + kSysItem - 1u) / kSysItem;
+            prev = o;
+          }
         }
       }
       const uint32_t last = omax > before ? omax : before;
@@ -1870,8 +1902,8 @@ __global__ void __launch_bounds__(NT) pf_global_prefix(StepArgs<T, S> a) {
     for (uint32_t c = b0; c < b1; c += CH) {
       uint32_t of[CH + 1];
 #pragma unroll
-      for (uint32_t k = 0; k < CH; ++k) of[k] = c + k < b1 ? a.gfirst[c + k] : next;
-      of[CH] = c + CH < b1 ? a.gfirst[c + CH] : next;
+      for (uint32_t k = 0; k < CH; ++k) of[k] = c + k < b1 ? (one ? fk[k] : a.gfirst[c + k]) : next;
+      of[CH] = !one && c + CH < b1 ? a.gfirst[c + CH] : next;
 #pragma unroll
       for (uint32_t k = 0; k < CH; ++k) {
         if (c + k < b1) {
